@@ -1,0 +1,225 @@
+/*
+ * gf2.h -- C ABI of libgf2, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of self-consistent second-order Green's function
+ * theory (GF2) of Phillips & Zgid, arXiv:1405.3273.
+ *
+ * The method (Implementation section and Supplementary Material):
+ *
+ *   Eq. (GF)         G(i w_n) = [ (mu + i w_n) S - F - Sigma(i w_n) ]^-1
+ *   Eq. (FockMatrix) F_ij = h_ij + sum_kl P_kl ( v_ijlk - v_iklj / 2 )
+ *   Eq. (Sigma)      Sigma_ij(tau) = - sum_{klmnpq} G_kl(tau) G_mn(tau) G_pq(-tau)
+ *                                    * v_imqk ( 2 v_lpnj - v_nplj )
+ *
+ * iterated as steps 1-3 of the Supplementary Material: a reference, an
+ * inner loop (2.a mu search, 2.b Fock rebuild) at fixed Sigma, then a new
+ * Sigma(tau) and its transform to the Matsubara axis.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - n basis functions (non-orthogonal AO basis, spin restricted).
+ * - Real matrices are FP64, row-major, [n][n].  v is FP64 [n][n][n][n],
+ *   v[i][j][k][l] = (ij|kl) in chemist notation with the 8-fold symmetry
+ *   of real integrals (the library relies on it).
+ * - Complex arrays are interleaved (re, im) FP64 pairs, [niw][n][n].
+ * - Matsubara grid: w_n = (2n+1) pi / beta, n = 0..niw-1 (only n >= 0 is
+ *   stored; X(-i w) = conj X(i w)).
+ * - Imaginary-time grid: uniform, tau_k = k beta / (ntau-1), k = 0..ntau-1,
+ *   both endpoints included; tau_0 and tau_{ntau-1} stand for 0+ and beta-.
+ *   G(-tau_k) = -G(tau_{ntau-1-k}) (antiperiodicity).
+ * - P is the spin-summed density (tr(P S) = nelec); G and Sigma are per spin.
+ * - Every array argument is a DEVICE pointer owned by the caller unless
+ *   the argument says "host".  The library never frees caller memory; it
+ *   owns only the workspaces inside a gf2_ctx.
+ * - Calls are ordered on the context's stream.  Calls that return host
+ *   scalars synchronise that stream before returning.
+ * - Every function returns a status code (GF2_OK = 0 or a negative
+ *   GF2_E* value).  No exception crosses the ABI.  gf2_last_error() returns
+ *   a message for the last failure on the calling thread.
+ */
+#ifndef GF2_H
+#define GF2_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GF2_OK          0
+#define GF2_EINVAL     -1   /* bad argument (sizes, NULL, enum value)            */
+#define GF2_EHIP       -2   /* a HIP runtime call failed                         */
+#define GF2_ENOMEM     -3   /* device allocation failed                          */
+#define GF2_ENOCONV    -4   /* an iteration hit its step limit                   */
+#define GF2_EBRACKET   -5   /* nelec outside [0, 2n] or the mu bracket failed    */
+#define GF2_ENONFINITE -6   /* a NaN/Inf appeared in a result                    */
+#define GF2_ESTATE     -7   /* call order: no system set on the context          */
+
+/* ---- enums ------------------------------------------------------------ */
+/* Arithmetic of the Sigma(tau) contraction (everything else is FP64). */
+#define GF2_PREC_FP64    0   /* FP64 MFMA                                        */
+#define GF2_PREC_FP32    1   /* FP32 MFMA, FP32 accumulate, FP64 final sums      */
+#define GF2_PREC_BF16X3  2   /* operands split hi+lo BF16, hi*hi+hi*lo+lo*hi     */
+                             /* on BF16 MFMA, FP32 accumulate, FP64 final sums   */
+
+#define GF2_TAU2IW 0         /* gf2_fourier: Sigma(tau) -> Sigma(i w), Sigma_1  */
+#define GF2_IW2TAU 1         /* gf2_fourier: G(i w) + tail moments -> G(tau)     */
+
+#define GF2_DYSON_TRACE  0   /* tr(P S) only                                     */
+#define GF2_DYSON_FULL   1   /* + G(i w) (optional) and P                        */
+#define GF2_DYSON_ENERGY 2   /* + the two-body Galitskii-Migdal energy            */
+
+#define GF2_MU_BISECT    0
+#define GF2_MU_ILLINOIS  1
+
+typedef struct gf2_ctx gf2_ctx;
+
+typedef struct {
+    int    n;       /* basis functions                                     */
+    int    nelec;   /* electrons (spin-summed)                             */
+    int    ntau;    /* tau points including both endpoints, >= 4           */
+    int    niw;     /* Matsubara frequencies (n >= 0), >= 1                */
+    double beta;    /* inverse temperature (1/Eh), > 0                     */
+} gf2_dims;
+
+typedef struct {
+    double tol_mu;       /* mu search: stop when the bracket is narrower      */
+    double tol_N;        /* mu search: accept when |tr(PS) - nelec| < tol_N    */
+    double tol_P;        /* inner loop: stop when max|P_out - P_in| < tol_P    */
+    double tol_E;        /* outer loop: |dE| threshold (reported, see below)   */
+    int    max_inner;    /* inner passes per outer iteration                   */
+    int    max_bisect;   /* mu evaluations per search                          */
+    double mu_halfwidth; /* initial half-width of the mu bracket (Eh)          */
+    double damp_P;       /* density damping a_P in the inner loop              */
+    int    mix_depth;    /* Pulay history length (1 = plain damping)           */
+    double damp_Sigma;   /* Sigma(tau) damping a_S in the outer loop           */
+    int    mu_method;    /* GF2_MU_BISECT or GF2_MU_ILLINOIS                   */
+    int    prec;         /* GF2_PREC_* for Sigma(tau)                          */
+} gf2_params;
+
+/* Outer-loop state, owned by the caller (device arrays [..][n][n]). */
+typedef struct {
+    double  mu;          /* in/out: chemical potential (start of the bracket)  */
+    double *F;           /* in/out device [n][n]: Fock matrix (h at the start) */
+    double *P;           /* in/out device [n][n]: density                      */
+    double *G_tau;       /* in/out device [ntau][n][n]                         */
+    double *Sigma_tau;   /* in/out device [ntau][n][n] (previous Sigma)        */
+    int     iteration;   /* in/out: completed outer iterations (0 = none)      */
+    int     has_P;       /* in/out: 0 until P holds a density                  */
+    double  energy;      /* in/out: energy of the last iteration               */
+} gf2_state;
+
+typedef struct {
+    double energy, e1b, e2b;     /* E = e1b + e2b (Eh)                         */
+    double dE, dP;               /* change vs the previous outer iteration     */
+    double mu;
+    int    n_inner;              /* inner passes                               */
+    int    n_eval;               /* tr(PS) evaluations in all mu searches      */
+    double ms_sigma, ms_fourier, ms_inner, ms_total;   /* wall-clock, ms       */
+} gf2_report;
+
+/* ---- context ------------------------------------------------------------
+ * gf2_ctx_create: bind a context to HIP device `device` and the stream
+ * `stream` (a hipStream_t passed as void*; NULL = the device's null stream).
+ * The context owns all workspaces; gf2_ctx_destroy frees them.
+ */
+int gf2_ctx_create(gf2_ctx **ctx, int device, void *stream);
+int gf2_ctx_destroy(gf2_ctx *ctx);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *gf2_last_error(void);
+
+/* gf2_set_system: the one-particle data and integrals of the problem
+ * (Implementation section: non-orthogonal AO basis with overlap S, core
+ * Hamiltonian h, AO integrals v).  S, h: device [n][n]; v: device
+ * [n][n][n][n] (ij|kl).  The data are copied; the context then also holds
+ * S^-1, the layouts of v used by the Sigma contraction (for all precisions)
+ * and the bracket W_lpnj = 2 v_lpnj - v_nplj of Eq. (Sigma).
+ * Errors: GF2_EINVAL for n < 1 or NULL pointers, GF2_EINVAL if S is
+ * singular.  Symmetry of S, h, v is assumed, not checked.
+ */
+int gf2_set_system(gf2_ctx *ctx, int n, const double *S, const double *h, const double *v);
+
+/* gf2_sigma_tau: Eq. (Sigma) at every tau point, G(-tau) from
+ * antiperiodicity.  G_tau: device [ntau][n][n] FP64 (symmetric).
+ * Sigma_tau: device [ntau][n][n] FP64 output (may not alias G_tau).
+ * prec: GF2_PREC_*.  dims->n must equal the n of gf2_set_system;
+ * nelec, niw are ignored.  Returns GF2_ENONFINITE if the result holds a
+ * NaN or Inf.
+ */
+int gf2_sigma_tau(gf2_ctx *ctx, const gf2_dims *dims, int prec,
+                  const double *G_tau, double *Sigma_tau);
+
+/* gf2_fourier: transforms between imaginary time and Matsubara frequency
+ * (Implementation section: FFT with an analytic high-frequency tail).
+ *   dir = GF2_TAU2IW: in = Sigma(tau) device [ntau][n][n] FP64;
+ *       out = Sigma(i w_n) device [niw][n][n] complex FP64 -- the Fourier
+ *       integral of the not-a-knot cubic spline of Sigma(tau), taken
+ *       exactly interval by interval; moment1_out (device [n][n], may be
+ *       NULL) = Sigma_1 = -(Sigma(0+) + Sigma(beta-)).  moments unused.
+ *   dir = GF2_IW2TAU: in = G(i w_n) device [niw][n][n] complex;
+ *       moments = device [3][n][n] = G1, G2, G3 of the tail
+ *       G ~ G1/(iw) + G2/(iw)^2 + G3/(iw)^3;
+ *       out = G(tau) device [ntau][n][n] FP64: the tail-subtracted
+ *       Matsubara sum plus the tail in closed form.  moment1_out unused.
+ * Works on any n (no system needed).
+ */
+int gf2_fourier(gf2_ctx *ctx, const gf2_dims *dims, int dir, const void *in,
+                const double *moments, void *out, double *moment1_out);
+
+/* gf2_dyson: Eq. (GF) at every Matsubara frequency for chemical potential
+ * mu, with the system's S and the given F (device [n][n]) and
+ * Sigma(i w) (device [niw][n][n] complex, NULL = 0) and Sigma_1 (device
+ * [n][n], NULL = 0).  Each inverse is a Gauss-Jordan elimination with
+ * partial pivoting in FP64.  The density is P = -2 G(beta-) with the tail
+ * summed exactly: P = (4/beta) sum_n Re[G - G1/(iw) - G2/(iw)^2 - G3/(iw)^3]
+ * + G1 - (beta/2) G2.
+ *   mode TRACE:  host_out[0] = tr(P S).  G_iw, P ignored.
+ *   mode FULL:   also writes P (device [n][n]) and, if G_iw != NULL,
+ *                G (device [niw][n][n] complex).
+ *   mode ENERGY: as FULL, and host_out[1] = E_2b = (1/beta) sum over all n
+ *                of tr[G Sigma] (truncated sum + exact 1/w^2 tail).
+ * host_out: host double[2].
+ */
+int gf2_dyson(gf2_ctx *ctx, const gf2_dims *dims, int mode, double mu,
+              const double *F, const void *Sigma_iw, const double *Sigma1,
+              void *G_iw, double *P, double *host_out);
+
+/* gf2_fock: Eq. (FockMatrix) F = h + J(P) - K(P)/2 for the system's h and
+ * v.  P, F: device [n][n] (may not alias).
+ */
+int gf2_fock(gf2_ctx *ctx, const double *P, double *F);
+
+/* gf2_density_fock: one pass of steps 2.a-2.b at fixed Sigma: find mu
+ * (bracketing search on tr(P(mu) S) = nelec, see gf2_params) starting from
+ * *mu_inout (host), then P_out = P(mu) (device [n][n]), F_out = F(P_out)
+ * (device [n][n], may be NULL) and, if G_iw_out != NULL, the G(i w) of that
+ * Dyson solve.  host_out (host double[4]) = { tr(P_out S), E_1b =
+ * tr[P_out (h + F_out)]/2 (0 if F_out is NULL), E_2b (0 if Sigma_iw is
+ * NULL), number of tr(PS) evaluations }.
+ * Errors: GF2_EBRACKET if nelec is outside [0, 2n] or no bracket is found,
+ * GF2_ENOCONV if the search exceeds max_bisect evaluations.
+ */
+int gf2_density_fock(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
+                     const double *F_in, const void *Sigma_iw, const double *Sigma1,
+                     double *mu_inout, double *P_out, double *F_out, void *G_iw_out,
+                     double *host_out);
+
+/* gf2_iterate: one outer iteration of the Supplementary Material's loop.
+ * iteration 0 (st->iteration == 0): the reference, step 2 with Sigma = 0
+ * from st->F (the core guess h) -- a finite-beta Hartree-Fock solution.
+ * iteration >= 1: Sigma(tau) from st->G_tau (step 3), damped against
+ * st->Sigma_tau from the second correlated iteration on, transformed to
+ * Sigma(i w); then the inner loop: passes of gf2_density_fock with the
+ * density mixed by damped Pulay/Anderson mixing of (P_in, P_out - P_in)
+ * (mix_depth 1 = the plain damping of the paper) until
+ * max|P_out - P_in| < tol_P; then E = E_1b + E_2b and the new G(tau).
+ * All state arrays are updated in place.  The report (host) carries the
+ * energy, its change, max|dP| against the previous iteration, mu, pass
+ * and evaluation counts and stage timings.
+ */
+int gf2_iterate(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
+                gf2_state *st, gf2_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GF2_H */

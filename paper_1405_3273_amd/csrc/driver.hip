@@ -1,0 +1,396 @@
+// The GF2 loop (Supplementary Material, steps 1-3) on top of the stage kernels.
+//
+// Host-side control only: every array operation runs on the device; the host
+// keeps scalars (mu bracket, residual norms, the small Pulay system).
+//
+// mu search (step 2.a): bracketing search on N(mu) = tr(P(mu) S) - nelec.
+//   Bracket [mu0 - hw, mu0 + hw]; while N(lo) > 0 move to [lo - w, lo], while
+//   N(hi) < 0 move to [hi, hi + w]; then evaluate an interior point (midpoint,
+//   or the Illinois regula-falsi point when it is strictly inside), accept it
+//   when |N| < tol_N, otherwise replace the end with the same sign (Illinois
+//   halves the value kept at an end that survives two steps in a row); stop
+//   at bracket width < tol_mu with the midpoint.
+// Inner loop (2.a-2.b): F = F(P_in) -> mu -> P_out; r = P_out - P_in; stop at
+//   max|r| < tol_P; next P_in = sum_a c_a (x_a + (1 - a_P) r_a) with
+//   c = argmin |sum c_a r_a|, sum c_a = 1 over the last mix_depth pairs.
+// Outer iteration (3): Sigma(tau) from G(tau), damping, Sigma(i w), inner
+//   loop, Galitskii-Migdal energy, G(tau).
+#include "gf2_internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+namespace gf2 {
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// N(mu) - nelec via the TRACE Dyson solve
+static int particle_excess(gf2_ctx *c, const gf2_dims *d, double mu, const double *F,
+                           const double2 *Sig, double *out) {
+    double r[2];
+    GF2_TRY(dyson_run(c, d, GF2_DYSON_TRACE, mu, F, Sig, nullptr, nullptr, nullptr, nullptr, r));
+    *out = r[0] - (double)d->nelec;
+    return GF2_OK;
+}
+
+static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
+                   const double2 *Sig, double mu0, double *mu_out, int *evals_out) {
+    const int n = c->n;
+    if (d->nelec < 0 || d->nelec > 2 * n)
+        return fail(GF2_EBRACKET, "mu search: nelec outside [0, 2n]");
+    int evals = 0;
+    double lo = mu0 - p->mu_halfwidth, hi = mu0 + p->mu_halfwidth;
+    double f_lo, f_hi;
+    GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
+    ++evals;
+    while (f_lo > 0.0) {
+        if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no lower bracket end");
+        const double w = hi - lo;
+        hi = lo;
+        lo = lo - w;
+        GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
+        ++evals;
+    }
+    GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
+    ++evals;
+    while (f_hi < 0.0) {
+        if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no upper bracket end");
+        const double w = hi - lo;
+        lo = hi;
+        hi = hi + w;
+        GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
+        ++evals;
+    }
+    int side = 0;
+    for (int step = 0; step < p->max_bisect; ++step) {
+        double mid = 0.5 * (lo + hi);
+        if (p->mu_method == GF2_MU_ILLINOIS && f_hi > f_lo) {
+            const double x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
+            if (lo < x && x < hi) mid = x;
+        }
+        double fm;
+        GF2_TRY(particle_excess(c, d, mid, F, Sig, &fm));
+        ++evals;
+        if (std::fabs(fm) < p->tol_N) {
+            *mu_out = mid;
+            *evals_out = evals;
+            return GF2_OK;
+        }
+        if (fm < 0.0) {
+            lo = mid;
+            f_lo = fm;
+            if (side == -1) f_hi *= 0.5;
+            side = -1;
+        } else {
+            hi = mid;
+            f_hi = fm;
+            if (side == 1) f_lo *= 0.5;
+            side = 1;
+        }
+        if (hi - lo < p->tol_mu) {
+            *mu_out = 0.5 * (lo + hi);
+            *evals_out = evals;
+            return GF2_OK;
+        }
+    }
+    return fail(GF2_ENOCONV, "mu search did not converge");
+}
+
+// One pass of 2.a-2.b without the Fock rebuild: mu, P_out, G(i w), moments, E_2b.
+static int density_pass(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
+                        const double2 *Sig, const double *Sig1, double *mu, double *P_out,
+                        double2 *G_iw, double *mom, double *trPS, double *e2b, int *evals) {
+    GF2_TRY(find_mu(c, d, p, F, Sig, *mu, mu, evals));
+    double r[2];
+    const int mode = Sig ? GF2_DYSON_ENERGY : GF2_DYSON_FULL;
+    GF2_TRY(dyson_run(c, d, mode, *mu, F, Sig, Sig1, G_iw, P_out, mom, r));
+    *trPS = r[0];
+    *e2b = r[1];
+    return GF2_OK;
+}
+
+// Solve the bordered Pulay system (oldest first) exactly as the oracle does.
+// Returns false if a pivot is negligible.
+static bool solve_pivoted(int n, std::vector<double> A, std::vector<double> b,
+                          std::vector<double> &x) {
+    double scale = 0.0;
+    for (double v : A) scale = std::fmax(scale, std::fabs(v));
+    for (int k = 0; k < n; ++k) {
+        int r = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[i * n + k]) > std::fabs(A[r * n + k])) r = i;
+        if (!(std::fabs(A[r * n + k]) > 1e-14 * scale)) return false;
+        if (r != k) {
+            for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[r * n + j]);
+            std::swap(b[k], b[r]);
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double f = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            b[i] -= f * b[k];
+        }
+    }
+    x.assign(n, 0.0);
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * x[j];
+        x[k] = s / A[k * n + k];
+    }
+    return true;
+}
+
+struct Pulay {
+    int depth = 1;
+    // device slots: x_a, r_a (ring of depth entries), host B_ab = <r_a, r_b>
+    std::vector<int> order;          // slot ids, oldest first
+    std::vector<double> B;           // depth x depth, indexed by slot
+    int free_slot() const {
+        for (int s = 0; s < depth; ++s) {
+            bool used = false;
+            for (int o : order) used |= (o == s);
+            if (!used) return s;
+        }
+        return -1;
+    }
+};
+
+static int pulay_step(gf2_ctx *c, Pulay &pl, double *slots, size_t ne, const double *P_in,
+                      const double *r, double damp, double *P_next) {
+    // push (P_in, r), dropping the oldest beyond depth
+    if ((int)pl.order.size() == pl.depth) pl.order.erase(pl.order.begin());
+    const int s = pl.free_slot();
+    double *xs = slots + (size_t)(2 * s) * ne, *rs = xs + ne;
+    GF2_TRY(copy_d2d(c, xs, P_in, ne * 8));
+    GF2_TRY(copy_d2d(c, rs, r, ne * 8));
+    pl.order.push_back(s);
+    for (int o : pl.order) {
+        double v;
+        GF2_TRY(dot(c, ne, rs, slots + (size_t)(2 * o + 1) * ne, &v));
+        pl.B[s * pl.depth + o] = v;
+        pl.B[o * pl.depth + s] = v;
+    }
+    std::vector<double> coef;
+    for (;;) {
+        const int k = (int)pl.order.size();
+        std::vector<double> A((k + 1) * (k + 1), 0.0), rhs(k + 1, 0.0), sol;
+        double dmax = 0.0;
+        for (int a = 0; a < k; ++a) dmax = std::fmax(dmax, pl.B[pl.order[a] * (pl.depth + 1)]);
+        dmax = std::fmax(dmax, 1e-300);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                A[a * (k + 1) + b] = pl.B[pl.order[a] * pl.depth + pl.order[b]] / dmax;
+        for (int a = 0; a < k; ++a) {
+            A[k * (k + 1) + a] = 1.0;
+            A[a * (k + 1) + k] = 1.0;
+        }
+        rhs[k] = 1.0;
+        if (solve_pivoted(k + 1, A, rhs, sol)) {
+            coef.assign(sol.begin(), sol.begin() + k);
+            break;
+        }
+        if (k == 1) {
+            coef.assign(1, 1.0);
+            break;
+        }
+        pl.order.erase(pl.order.begin(), pl.order.end() - 1);
+    }
+    // P_next = sum_a c_a (x_a + (1 - damp) r_a)
+    GF2_TRY(fill_zero(c, P_next, ne * 8));
+    double *tmp = c->it_tmp.as<double>() + 1024;   // scratch after the reduction area
+    for (size_t a = 0; a < coef.size(); ++a) {
+        const int o = pl.order[a];
+        const double *xa = slots + (size_t)(2 * o) * ne, *ra = xa + ne;
+        GF2_TRY(copy_d2d(c, tmp, xa, ne * 8));
+        GF2_TRY(axpby(c, ne, 1.0 - damp, ra, 1.0, tmp));
+        GF2_TRY(axpby(c, ne, coef[a], tmp, 1.0, P_next));
+    }
+    return GF2_OK;
+}
+
+static int check_dims(gf2_ctx *c, const gf2_dims *d, const char *who) {
+    if (!c || !d) return fail(GF2_EINVAL, std::string(who) + ": NULL argument");
+    if (!c->has_system) return fail(GF2_ESTATE, std::string(who) + ": no system set");
+    if (d->n != c->n) return fail(GF2_EINVAL, std::string(who) + ": dims->n differs from the system");
+    if (d->ntau < 4 || d->niw < 1 || !(d->beta > 0.0))
+        return fail(GF2_EINVAL, std::string(who) + ": bad dims (ntau >= 4, niw >= 1, beta > 0)");
+    if (d->nelec < 0 || d->nelec > 2 * d->n)
+        return fail(GF2_EBRACKET, std::string(who) + ": nelec outside [0, 2n]");
+    return GF2_OK;
+}
+
+static int check_params(const gf2_params *p, const char *who) {
+    if (!p) return fail(GF2_EINVAL, std::string(who) + ": params is NULL");
+    if (!(p->tol_mu > 0) || !(p->tol_N > 0) || !(p->tol_P > 0) || p->max_inner < 1 ||
+        p->max_bisect < 1 || !(p->mu_halfwidth > 0) || p->mix_depth < 1 || p->mix_depth > 32 ||
+        !(p->damp_P >= 0 && p->damp_P < 1) || !(p->damp_Sigma >= 0 && p->damp_Sigma < 1) ||
+        (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS) ||
+        p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16X3)
+        return fail(GF2_EINVAL, std::string(who) + ": bad parameters");
+    return GF2_OK;
+}
+
+}  // namespace gf2
+
+using namespace gf2;
+
+extern "C" int gf2_density_fock(gf2_ctx *c, const gf2_dims *d, const gf2_params *p,
+                                const double *F_in, const void *Sigma_iw, const double *Sigma1,
+                                double *mu_inout, double *P_out, double *F_out, void *G_iw_out,
+                                double *host_out) {
+    GF2_TRY(check_dims(c, d, "gf2_density_fock"));
+    GF2_TRY(check_params(p, "gf2_density_fock"));
+    if (!F_in || !mu_inout || !P_out || !host_out)
+        return fail(GF2_EINVAL, "gf2_density_fock: NULL argument");
+    GF2_HIP(hipSetDevice(c->device));
+    const size_t ne = (size_t)c->n * c->n;
+    GF2_TRY(c->it_mom.ensure(3 * ne * 8));
+    double trPS = 0, e2b = 0;
+    int evals = 0;
+    double mu = *mu_inout;
+    GF2_TRY(density_pass(c, d, p, F_in, static_cast<const double2 *>(Sigma_iw), Sigma1, &mu, P_out,
+                         static_cast<double2 *>(G_iw_out), c->it_mom.as<double>(), &trPS, &e2b,
+                         &evals));
+    *mu_inout = mu;
+    double e1b = 0.0;
+    if (F_out) {
+        GF2_TRY(fock_run(c, P_out, F_out));
+        double ph, pf;
+        GF2_TRY(dot(c, ne, P_out, c->h.as<double>(), &ph));
+        GF2_TRY(dot(c, ne, P_out, F_out, &pf));
+        e1b = 0.5 * (ph + pf);
+    }
+    host_out[0] = trPS;
+    host_out[1] = e1b;
+    host_out[2] = e2b;
+    host_out[3] = (double)evals;
+    return GF2_OK;
+}
+
+extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
+                           gf2_report *rep) {
+    GF2_TRY(check_dims(c, d, "gf2_iterate"));
+    GF2_TRY(check_params(p, "gf2_iterate"));
+    if (!st || !rep || !st->F || !st->P || !st->G_tau || !st->Sigma_tau)
+        return fail(GF2_EINVAL, "gf2_iterate: NULL state array or report");
+    GF2_HIP(hipSetDevice(c->device));
+    const double t0 = now_ms();
+    const int n = c->n;
+    const size_t ne = (size_t)n * n;
+    const size_t nt = (size_t)d->ntau * ne;
+    GF2_TRY(c->it_Pout.ensure(ne * 8));
+    GF2_TRY(c->it_Pin.ensure(ne * 8));
+    GF2_TRY(c->it_F.ensure(ne * 8));
+    GF2_TRY(c->it_mom.ensure(3 * ne * 8));
+    GF2_TRY(c->it_Sig1.ensure(ne * 8));
+    GF2_TRY(c->it_G_iw.ensure((size_t)d->niw * ne * 16));
+    GF2_TRY(c->it_hist.ensure((size_t)2 * p->mix_depth * ne * 8));
+    GF2_TRY(c->it_tmp.ensure((1024 + ne) * 8));
+
+    double t_sig = 0.0, t_four = 0.0;
+    const double2 *Sig = nullptr;
+    const double *Sig1 = nullptr;
+    if (st->iteration > 0) {
+        GF2_TRY(c->it_Sig_new.ensure(nt * 8));
+        GF2_TRY(c->it_Sig_iw.ensure((size_t)d->niw * ne * 16));
+        double *Snew = c->it_Sig_new.as<double>();
+        GF2_HIP(hipStreamSynchronize(c->stream));
+        const double ts = now_ms();
+        GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, Snew));
+        GF2_HIP(hipStreamSynchronize(c->stream));
+        t_sig = now_ms() - ts;
+        int bad = 0;
+        GF2_TRY(any_nonfinite(c, nt, Snew, &bad));
+        if (bad) return fail(GF2_ENONFINITE, "gf2_iterate: non-finite self-energy");
+        if (st->iteration >= 2 && p->damp_Sigma > 0.0)
+            GF2_TRY(axpby(c, nt, p->damp_Sigma, st->Sigma_tau, 1.0 - p->damp_Sigma, Snew));
+        GF2_TRY(copy_d2d(c, st->Sigma_tau, Snew, nt * 8));
+        const double tf = now_ms();
+        GF2_TRY(fourier_tau2iw(c, d, st->Sigma_tau, c->it_Sig_iw.as<double2>(),
+                               c->it_Sig1.as<double>()));
+        GF2_HIP(hipStreamSynchronize(c->stream));
+        t_four += now_ms() - tf;
+        Sig = c->it_Sig_iw.as<double2>();
+        Sig1 = c->it_Sig1.as<double>();
+    }
+
+    // ---- inner loop ----
+    const double ti = now_ms();
+    double *Pin = c->it_Pin.as<double>(), *Pout = c->it_Pout.as<double>(), *F = c->it_F.as<double>();
+    bool have_Pin = st->has_P != 0;
+    if (have_Pin) GF2_TRY(copy_d2d(c, Pin, st->P, ne * 8));
+    GF2_TRY(copy_d2d(c, F, st->F, ne * 8));
+    double mu = st->mu;
+    Pulay pl;
+    pl.depth = p->mix_depth;
+    pl.B.assign((size_t)pl.depth * pl.depth, 0.0);
+    double *slots = c->it_hist.as<double>();
+    double *r = c->it_tmp.as<double>() + 1024;   // residual; pulay_step uses its own tmp below
+    GF2_TRY(c->it_tmp.ensure((1024 + 2 * ne) * 8));
+    r = c->it_tmp.as<double>() + 1024 + ne;
+    int n_inner = 0, n_eval = 0;
+    double e2b = 0.0, trPS = 0.0;
+    bool converged = false;
+    for (int it = 1; it <= p->max_inner; ++it) {
+        int ev = 0;
+        GF2_TRY(density_pass(c, d, p, F, Sig, Sig1, &mu, Pout, c->it_G_iw.as<double2>(),
+                             c->it_mom.as<double>(), &trPS, &e2b, &ev));
+        n_eval += ev;
+        n_inner = it;
+        if (!have_Pin) {
+            GF2_TRY(copy_d2d(c, Pin, Pout, ne * 8));
+            have_Pin = true;
+        } else {
+            double dmax;
+            GF2_TRY(max_abs_diff(c, ne, Pout, Pin, &dmax));
+            if (dmax < p->tol_P) {
+                converged = true;
+                break;
+            }
+            GF2_TRY(copy_d2d(c, r, Pout, ne * 8));
+            GF2_TRY(axpby(c, ne, -1.0, Pin, 1.0, r));
+            GF2_TRY(pulay_step(c, pl, slots, ne, Pin, r, p->damp_P, Pin));
+        }
+        GF2_TRY(fock_run(c, Pin, F));
+    }
+    if (!converged) return fail(GF2_ENOCONV, "gf2_iterate: inner loop did not converge");
+    GF2_TRY(fock_run(c, Pout, F));
+    double ph, pf;
+    GF2_TRY(dot(c, ne, Pout, c->h.as<double>(), &ph));
+    GF2_TRY(dot(c, ne, Pout, F, &pf));
+    const double e1b = 0.5 * (ph + pf);
+    const double t_inner = now_ms() - ti;
+
+    // ---- G(tau) for the next Sigma ----
+    const double tf2 = now_ms();
+    GF2_TRY(fourier_iw2tau(c, d, c->it_G_iw.as<double2>(), c->it_mom.as<double>(), st->G_tau));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    t_four += now_ms() - tf2;
+
+    double dP = INFINITY;
+    if (st->has_P) GF2_TRY(max_abs_diff(c, ne, Pout, st->P, &dP));
+    GF2_TRY(copy_d2d(c, st->P, Pout, ne * 8));
+    GF2_TRY(copy_d2d(c, st->F, F, ne * 8));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    const double E = e1b + e2b;
+    rep->energy = E;
+    rep->e1b = e1b;
+    rep->e2b = e2b;
+    rep->dE = std::isfinite(st->energy) ? E - st->energy : INFINITY;
+    rep->dP = dP;
+    rep->mu = mu;
+    rep->n_inner = n_inner;
+    rep->n_eval = n_eval;
+    rep->ms_sigma = t_sig;
+    rep->ms_fourier = t_four;
+    rep->ms_inner = t_inner;
+    rep->ms_total = now_ms() - t0;
+    st->mu = mu;
+    st->energy = E;
+    st->has_P = 1;
+    st->iteration += 1;
+    return GF2_OK;
+}

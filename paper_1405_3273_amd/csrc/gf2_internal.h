@@ -1,0 +1,120 @@
+// Internal declarations of libgf2 (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gf2.h"
+
+namespace gf2 {
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define GF2_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) return ::gf2::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define GF2_TRY(call)                                                        \
+    do {                                                                     \
+        int rc_ = (call);                                                    \
+        if (rc_ != GF2_OK) return rc_;                                       \
+    } while (0)
+
+// ---- device buffers ---------------------------------------------------------
+// Grow-only device allocation owned by the context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Sigma(tau) arithmetic modes (match GF2_PREC_*).
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2 };
+
+}  // namespace gf2
+
+struct gf2_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    // ---- system (gf2_set_system) ----
+    int n = 0;
+    bool has_system = false;
+    gf2::DevBuf S, Sinv, h, v;            // FP64
+    std::vector<double> S_host, Sinv_host, h_host;
+
+    // Layouts for the Sigma contraction, built once per system:
+    //   V1[m][q][k][i] = v_imqk     (first index transform contracts m)
+    //   W2[n][p][l][j] = 2 v_lpnj - v_nplj
+    gf2::DevBuf V1_64, W2_64, V1_32, W2_32;
+    bool have_f32_layouts = false;
+
+    // ---- workspaces (grow-only) ----
+    gf2::DevBuf sig_T1, sig_T2, sig_G, sig_Gb, sig_part;
+    gf2::DevBuf four_c, four_C, four_fold, four_twid;
+    gf2::DevBuf dys_part, dys_X, dys_aux, dys_out;
+    gf2::DevBuf fock_part;
+    gf2::DevBuf it_Sig_iw, it_G_iw, it_Sig1, it_mom, it_Sig_new, it_Pout, it_Pin, it_F, it_tmp;
+    gf2::DevBuf it_hist;                  // Pulay history on the device: [2*depth][n][n]
+    gf2::DevBuf host_stage;               // unused placeholder for pinned staging
+};
+
+namespace gf2 {
+
+// ---- small shared kernels (common.hip) ---------------------------------------
+int copy_d2d(gf2_ctx *c, void *dst, const void *src, size_t bytes);
+int fill_zero(gf2_ctx *c, void *dst, size_t bytes);
+// y = a*x + b*y, n doubles
+int axpby(gf2_ctx *c, size_t n, double a, const double *x, double b, double *y);
+// max |a - b| over n doubles (host result; synchronises)
+int max_abs_diff(gf2_ctx *c, size_t n, const double *a, const double *b, double *out);
+// 1 if any element of x[n] is not finite (host result; synchronises)
+int any_nonfinite(gf2_ctx *c, size_t n, const double *x, int *out);
+// out = sum_i a_i * b_i (host result; synchronises)
+int dot(gf2_ctx *c, size_t n, const double *a, const double *b, double *out);
+// small dense matmul on the device: C = A * B (n x n FP64)
+int matmul_nn(gf2_ctx *c, int n, const double *A, const double *B, double *C);
+
+// Plain FP64 GEMM on MFMA: C[m*ldc + n] = alpha * sum_k A[k*lda + m] B[k*ldb + n]
+struct GemmArgsF64 {
+    const double *A; long long lda;
+    const double *B; long long ldb;
+    double *C; long long ldc;
+    int M, N, K;
+    double alpha;
+};
+int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a);
+
+// ---- stages ---------------------------------------------------------------------
+int sigma_build_layouts(gf2_ctx *c, bool want_f32);
+int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau);
+
+int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2 *Sig_iw,
+                   double *Sig1);
+int fourier_iw2tau(gf2_ctx *c, const gf2_dims *d, const double2 *G_iw, const double *mom,
+                   double *G_tau);
+
+// Dyson over all frequencies.  mode = GF2_DYSON_*.  out[0] = tr(PS),
+// out[1] = E_2b (ENERGY).  If mom_out != NULL the tail moments G1,G2,G3
+// of this (mu, F, Sigma_1) are written there ([3][n][n]).
+int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
+              const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
+              double *mom_out, double *out);
+
+int fock_run(gf2_ctx *c, const double *P, double *F);
+
+// trigamma(x) for x > 0 (host)
+double trigamma(double x);
+
+}  // namespace gf2

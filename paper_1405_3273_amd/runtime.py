@@ -1,0 +1,125 @@
+"""Python front end of libgf2: owns a context, the system and the loop state
+as torch device tensors and calls the C ABI.  Argument marshalling only.
+"""
+from __future__ import annotations
+
+import math
+
+from . import _lib as L
+
+
+class Gf2:
+    """One GF2 problem on one GPU.
+
+    ``S``, ``h``: [n][n] float64; ``v``: [n][n][n][n] float64 (ij|kl); any
+    device or host tensor/array (copied to ``device``).
+    """
+
+    def __init__(self, S, h, v, nelec, beta, niw, ntau, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        t = lambda x: torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
+        self.S, self.h, self.v = t(S), t(h), t(v)
+        self.n = int(self.S.shape[0])
+        self.dims = L.make_dims(self.n, nelec, ntau, niw, beta)
+        self.ctx = L.gf2_ctx_create(device)
+        L.gf2_set_system(self.ctx, self.S, self.h, self.v)
+        self.state = None
+        self._keep = None
+
+    # -- context -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            L.gf2_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, *shape, complex_=False):
+        dt = self.torch.complex128 if complex_ else self.torch.float64
+        return self.torch.empty(*shape, dtype=dt, device=self.device)
+
+    def dims_with(self, **kw):
+        d = self.dims
+        args = dict(n=d.n, nelec=d.nelec, ntau=d.ntau, niw=d.niw, beta=d.beta)
+        args.update(kw)
+        return L.make_dims(**args)
+
+    # -- single stages ---------------------------------------------------------
+    def sigma_tau(self, G_tau, prec="fp32", out=None):
+        ntau = int(G_tau.shape[0])
+        out = self._empty(ntau, self.n, self.n) if out is None else out
+        L.gf2_sigma_tau(self.ctx, self.dims_with(ntau=ntau), prec, G_tau, out)
+        return out
+
+    def tau_to_iw(self, Sig_tau, niw=None, beta=None):
+        ntau = int(Sig_tau.shape[0])
+        d = self.dims_with(ntau=ntau, niw=niw or self.dims.niw, beta=beta or self.dims.beta)
+        out = self._empty(d.niw, self.n, self.n, complex_=True)
+        s1 = self._empty(self.n, self.n)
+        L.gf2_fourier(self.ctx, d, L.GF2_TAU2IW, Sig_tau, None, out, s1)
+        return out, s1
+
+    def iw_to_tau(self, G_iw, moments, ntau=None, beta=None):
+        d = self.dims_with(niw=int(G_iw.shape[0]), ntau=ntau or self.dims.ntau,
+                           beta=beta or self.dims.beta)
+        out = self._empty(d.ntau, self.n, self.n)
+        L.gf2_fourier(self.ctx, d, L.GF2_IW2TAU, G_iw, moments, out)
+        return out
+
+    def dyson(self, mode, mu, F, Sigma_iw=None, Sigma1=None, want_G=False):
+        P = self._empty(self.n, self.n) if mode != L.GF2_DYSON_TRACE else None
+        G = self._empty(self.dims.niw, self.n, self.n, complex_=True) if want_G else None
+        r = L.gf2_dyson(self.ctx, self.dims, mode, mu, F, Sigma_iw, Sigma1, G, P)
+        return r, P, G
+
+    def fock(self, P):
+        F = self._empty(self.n, self.n)
+        L.gf2_fock(self.ctx, P, F)
+        return F
+
+    def density_fock(self, params, F_in, mu, Sigma_iw=None, Sigma1=None, want_G=False):
+        P = self._empty(self.n, self.n)
+        F = self._empty(self.n, self.n)
+        G = self._empty(self.dims.niw, self.n, self.n, complex_=True) if want_G else None
+        mu, info = L.gf2_density_fock(self.ctx, self.dims, params, F_in, Sigma_iw, Sigma1, mu,
+                                      P, F, G)
+        return mu, P, F, G, info
+
+    # -- the loop ----------------------------------------------------------------
+    def reset(self, mu0=0.0):
+        """Core guess F = h, no density yet, iteration 0 next."""
+        n, ntau = self.n, self.dims.ntau
+        self.F = self.h.clone()
+        self.P = self.torch.zeros(n, n, dtype=self.torch.float64, device=self.device)
+        self.G_tau = self.torch.zeros(ntau, n, n, dtype=self.torch.float64, device=self.device)
+        self.Sigma_tau = self.torch.zeros_like(self.G_tau)
+        self.state = L.gf2_state(float(mu0), self.F.data_ptr(), self.P.data_ptr(),
+                                 self.G_tau.data_ptr(), self.Sigma_tau.data_ptr(), 0, 0,
+                                 float("nan"))
+
+    def iterate(self, params) -> L.gf2_report:
+        if self.state is None:
+            self.reset()
+        return L.gf2_iterate(self.ctx, self.dims, params, self.state)
+
+    def run(self, params, max_outer=50, tol_E=None, callback=None):
+        tol_E = params.tol_E if tol_E is None else tol_E
+        reps = []
+        for _ in range(max_outer):
+            r = self.iterate(params)
+            reps.append(r)
+            if callback:
+                callback(self, r)
+            if self.state.iteration > 1 and abs(r.dE) < tol_E and r.dP < params.tol_P:
+                return reps, True
+        return reps, False
+
+    @property
+    def mu(self):
+        return self.state.mu if self.state is not None else math.nan

@@ -1,0 +1,240 @@
+"""GPU parity of each C-ABI call against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import generic_system, random_tau_stack, random_symmetric
+
+pytestmark = pytest.mark.gpu
+
+TOL_SIGMA = {"fp64": 1e-12, "fp32": 3e-5, "bf16x3": 3e-4}   # max|err| / max|ref|
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _gf2(sysm, **kw):
+    from paper_1405_3273_amd.runtime import Gf2
+    args = dict(nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw, ntau=sysm.ntau)
+    args.update(kw)
+    return Gf2(sysm.S, sysm.h, sysm.v, **args)
+
+
+def _dev(torch, x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def _relerr(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# Eq. (Sigma)
+
+@pytest.mark.parametrize("n,ntau", [(1, 5), (3, 9), (10, 257), (17, 12), (33, 6), (40, 5)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_sigma_tau_matches_oracle(torch, n, ntau, prec):
+    print(f"sigma n={n} ntau={ntau} prec={prec}", flush=True)
+    s = generic_system(n, 500 + n, naux=max(2, 2 * n), beta=20.0, ntau=ntau)
+    rng = np.random.default_rng(n)
+    Gt = random_tau_stack(rng, ntau, n)
+    ref = O.sigma_tau(Gt, s.v)
+    g = _gf2(s)
+    got = g.sigma_tau(_dev(torch, Gt), prec).cpu().numpy()
+    err = _relerr(got, ref)
+    print(f"  rel err {err:.3e}")
+    assert err <= TOL_SIGMA[prec]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_sigma_tau_n100_sampled(torch, prec):
+    """N=100 (the benchmark size) on a few tau points, all elements."""
+    print(f"sigma n=100 prec={prec}", flush=True)
+    n, ntau = 100, 6
+    s = generic_system(n, 300, naux=400, half_band=12, diag=(-3.0, -0.3), beta=200.0, ntau=ntau)
+    rng = np.random.default_rng(7)
+    Gt = random_tau_stack(rng, ntau, n, scale=0.05)
+    ref = O.sigma_tau(Gt, s.v, taus=[0, 2, 5])
+    g = _gf2(s)
+    got = g.sigma_tau(_dev(torch, Gt), prec).cpu().numpy()[[0, 2, 5]]
+    err = _relerr(got, ref)
+    print(f"  rel err {err:.3e}")
+    assert err <= TOL_SIGMA[prec]
+    g.close()
+
+
+def test_sigma_deterministic(torch):
+    s = generic_system(12, 3, ntau=9)
+    Gt = _dev(torch, random_tau_stack(np.random.default_rng(1), 9, 12))
+    g = _gf2(s)
+    a = g.sigma_tau(Gt, "fp32").cpu().numpy()
+    b = g.sigma_tau(Gt, "fp32").cpu().numpy()
+    assert np.array_equal(a, b)
+    g.close()
+
+
+def test_sigma_rejects_bad_arguments(torch):
+    from paper_1405_3273_amd import Gf2Error
+    s = generic_system(4, 3, ntau=9)
+    g = _gf2(s)
+    Gt = _dev(torch, random_tau_stack(np.random.default_rng(1), 3, 4))   # ntau = 3 < 4
+    with pytest.raises(Gf2Error):
+        g.sigma_tau(Gt, "fp32")
+    Gt = _dev(torch, random_tau_stack(np.random.default_rng(1), 9, 4))
+    with pytest.raises(Gf2Error):
+        g.sigma_tau(Gt, 7)
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# transforms
+
+@pytest.mark.parametrize("n,ntau,niw,beta", [(1, 17, 64, 20.0), (5, 33, 300, 10.0),
+                                             (4, 37, 20, 7.5), (10, 257, 2048, 50.0)])
+def test_tau_to_iw_matches_oracle(torch, n, ntau, niw, beta):
+    s = generic_system(n, 11, beta=beta, niw=niw, ntau=ntau)
+    rng = np.random.default_rng(2)
+    tau = O.tau_grid(beta, ntau)
+    # smooth, decaying data plus noise
+    Y = random_tau_stack(rng, ntau, n) * np.exp(-tau / beta)[:, None, None]
+    ref, s1 = O.sigma_tau_to_iw(Y, beta, niw)
+    g = _gf2(s)
+    got, g1 = g.tau_to_iw(_dev(torch, Y))
+    err = _relerr(got.cpu().numpy(), ref)
+    print(f"tau->iw n={n} ntau={ntau} niw={niw}: rel err {err:.3e}")
+    assert err < 1e-12
+    assert np.max(np.abs(g1.cpu().numpy() - s1)) < 1e-14
+    g.close()
+
+
+@pytest.mark.parametrize("n,ntau,niw,beta", [(1, 17, 64, 20.0), (5, 33, 300, 10.0),
+                                             (4, 37, 20, 7.5), (10, 257, 2048, 50.0)])
+def test_iw_to_tau_matches_oracle(torch, n, ntau, niw, beta):
+    s = generic_system(n, 12, beta=beta, niw=niw, ntau=ntau)
+    rng = np.random.default_rng(3)
+    iw = 1j * O.matsubara(beta, niw)[:, None, None]
+    G1 = np.linalg.inv(s.S)
+    G2 = random_symmetric(rng, n)
+    G3 = random_symmetric(rng, n)
+    X = random_symmetric(rng, n) + 1j * random_symmetric(rng, n)
+    Giw = G1 / iw + G2 / iw ** 2 + G3 / iw ** 3 + X / iw ** 4
+    ref = O.g_iw_to_tau(Giw, G1, G2, G3, beta, ntau)
+    g = _gf2(s)
+    mom = _dev(torch, np.stack([G1, G2, G3]))
+    got = g.iw_to_tau(_dev(torch, Giw), mom).cpu().numpy()
+    err = _relerr(got, ref)
+    print(f"iw->tau n={n} ntau={ntau} niw={niw}: rel err {err:.3e}")
+    assert err < 1e-12
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Eq. (GF)
+
+def _sigma_iw_case(s, rng, scale=0.05):
+    """A smooth self-energy on the Matsubara axis from a decaying Sigma(tau)."""
+    tau = O.tau_grid(s.beta, s.ntau)
+    Y = -scale * random_tau_stack(rng, s.ntau, s.n, scale=1.0) ** 2
+    Y = Y * (np.exp(-tau) + np.exp(-(s.beta - tau)))[:, None, None]
+    return O.sigma_tau_to_iw(Y, s.beta, s.niw)
+
+
+@pytest.mark.parametrize("n", [1, 10, 25, 26, 27, 52, 53, 100])
+def test_dyson_modes_match_oracle(torch, n):
+    from paper_1405_3273_amd import _lib as L
+    print(f"dyson n={n}", flush=True)
+    niw = 512 if n >= 50 else 1024
+    s = generic_system(n, 40 + n, beta=30.0, niw=niw, ntau=65)
+    rng = np.random.default_rng(n)
+    Siw, S1 = _sigma_iw_case(s, rng)
+    F = s.h + 0.1 * random_symmetric(rng, n)
+    mu = float(np.mean(np.diag(F)))
+    g = _gf2(s)
+    Fd, Sd, S1d = _dev(torch, F), _dev(torch, Siw), _dev(torch, S1)
+    # oracle
+    G = O.green_iw(mu, s.S, F, Siw, s.beta, niw)
+    mom = O.tail_moments(s.S, F, mu, S1)
+    P = O.density_from_giw(G, *mom, s.beta)
+    N = float(np.trace(P @ s.S))
+    E2 = O.e_two_body(G, Siw, mom[0], S1, s.beta)
+    (tr, _), _, _ = g.dyson(L.GF2_DYSON_TRACE, mu, Fd, Sd, S1d)
+    assert tr == pytest.approx(N, rel=1e-11, abs=1e-11)
+    (tr2, e2), Pg, Gg = g.dyson(L.GF2_DYSON_ENERGY, mu, Fd, Sd, S1d, want_G=True)
+    errP = np.max(np.abs(Pg.cpu().numpy() - P))
+    errG = _relerr(Gg.cpu().numpy(), G)
+    print(f"  N {tr:.12f}/{N:.12f}  P err {errP:.2e}  G rel err {errG:.2e}  E2 {e2:.12f}/{E2:.12f}")
+    assert errP < 1e-11 * max(1.0, np.max(np.abs(P)))
+    assert errG < 1e-12
+    assert tr2 == pytest.approx(N, rel=1e-11, abs=1e-11)
+    assert e2 == pytest.approx(E2, rel=1e-10, abs=1e-12)
+    g.close()
+
+
+def test_dyson_without_sigma_is_hartree_fock(torch):
+    from paper_1405_3273_amd import _lib as L
+    from oracle import reference as R
+    s = generic_system(8, 5, beta=20.0, niw=4096, ntau=33)
+    eps, _ = R.generalized_eig(s.h, s.S)
+    mu = R.mu_closed_form(eps, s.nelec, s.beta)
+    g = _gf2(s)
+    (tr, _), P, _ = g.dyson(L.GF2_DYSON_FULL, mu, _dev(torch, s.h))
+    assert tr == pytest.approx(s.nelec, abs=1e-8)
+    assert np.max(np.abs(P.cpu().numpy() - R.hf_density(s.S, s.h, mu, s.beta))) < 1e-8
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Eq. (FockMatrix)
+
+@pytest.mark.parametrize("n", [1, 5, 10, 33, 100])
+def test_fock_matches_oracle(torch, n):
+    s = generic_system(n, 70 + n, naux=max(2, n))
+    P = random_symmetric(np.random.default_rng(n), n)
+    g = _gf2(s)
+    got = g.fock(_dev(torch, P)).cpu().numpy()
+    ref = O.fock(s.h, s.v, P)
+    assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# one pass of 2.a-2.b
+
+@pytest.mark.parametrize("method", ["bisect", "illinois"])
+def test_density_fock_matches_oracle(torch, method):
+    from paper_1405_3273_amd import make_params
+    s = generic_system(10, 0, naux=30, beta=50.0, niw=2048, ntau=257)
+    rng = np.random.default_rng(4)
+    Siw, S1 = _sigma_iw_case(s, rng)
+    F = O.fock(s.h, s.v, 0.5 * np.eye(s.n) * s.nelec / s.n)
+    prm = O.Params(mu_method=method)
+    mu_ref, ev = O.find_mu(s.nelec, s.S, F, Siw, S1, s.beta, s.niw, -1.0,
+                           halfwidth=prm.mu_halfwidth, tol_mu=prm.tol_mu, tol_N=prm.tol_N,
+                           max_steps=prm.max_bisect, method=method)
+    G = O.green_iw(mu_ref, s.S, F, Siw, s.beta, s.niw)
+    P_ref = O.density_from_giw(G, *O.tail_moments(s.S, F, mu_ref, S1), s.beta)
+    g = _gf2(s)
+    mu, P, Fo, _, info = g.density_fock(make_params(mu_method=method), _dev(torch, F), -1.0,
+                                        _dev(torch, Siw), _dev(torch, S1))
+    print(f"mu {mu:.15f} / {mu_ref:.15f}, evals {info['n_eval']} / {ev}")
+    assert mu == pytest.approx(mu_ref, abs=1e-10)
+    assert np.max(np.abs(P.cpu().numpy() - P_ref)) < 1e-9
+    assert np.max(np.abs(Fo.cpu().numpy() - O.fock(s.h, s.v, P_ref))) < 1e-9
+    assert info["trPS"] == pytest.approx(s.nelec, abs=1e-9)
+    g.close()
+
+
+def test_density_fock_rejects_impossible_electron_count(torch):
+    from paper_1405_3273_amd import Gf2Error, make_params
+    from paper_1405_3273_amd.runtime import Gf2
+    s = generic_system(4, 1, niw=64, ntau=9)
+    g = Gf2(s.S, s.h, s.v, nelec=9, beta=s.beta, niw=s.niw, ntau=s.ntau)
+    with pytest.raises(Gf2Error) as e:
+        g.density_fock(make_params(), _dev(torch, s.h), 0.0)
+    assert e.value.code == -5
+    g.close()
