@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""GF2 benchmark on one MI355X.
+
+A step is one outer GF2 iteration of the Supplementary Material's loop on
+the N=100 molecule-shaped workload (100 electrons, banded h, naux=400,
+beta=200, 16384 Matsubara frequencies, 512 tau points, seed 300):
+Eq. (Sigma) at every tau point, Sigma(tau) -> Sigma(i w), the inner loop
+(mu search + Dyson + Fock, Pulay-mixed density) to max|dP| < 1e-10, the
+Galitskii-Migdal energy and G(i w) -> G(tau).  Warm-up iterations include
+the Hartree-Fock reference (iteration 0).  Inputs are resident in HBM before
+the timed region.
+
+Prints one JSON line (see --help for the knobs).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GF2 iterations/s + Σ(τ) TFLOP/s at N=100,nτ=512; FP32/BF16-split vs FP64"
+
+PEAK = {  # MI355X published dense peaks
+    "fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "hbm": 8.0e12, "fp64_vector": 78.6e12,
+}
+
+WORKLOADS = {
+    "n100": ("molecule_n100", "generic-n100: N=100, 100 electrons, half-band 12, naux=400, "
+             "beta=200, niw=16384, ntau=512, seed 300"),
+    "n10": ("small_molecule", "generic-n10: N=10, 10 electrons, naux=30, beta=50, niw=2048, "
+            "ntau=257, seed 0"),
+    "n160": ("molecule_n160", "generic-n160: N=160, 160 electrons, half-band 16, naux=640, "
+             "beta=200, niw=16384, ntau=512, seed 400"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sigma_flops(n, ntau):
+    return 8.0 * n ** 5 * ntau
+
+
+def cpu_baseline(sysm, counts, sample_tau=3, sample_freq=512):
+    """The oracle, as it stands, on a bounded sample of one outer iteration:
+    Eq. (Sigma) at `sample_tau` tau points and Eq. (GF) (+ density trace) at
+    `sample_freq` frequencies; scaled to a whole iteration with the numbers
+    of Dyson solves the GPU iteration performed."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    n, ntau, niw = sysm.n, sysm.ntau, sysm.niw
+    rng = np.random.default_rng(0)
+    Gt = 0.05 * rng.standard_normal((ntau, n, n))
+    Gt = 0.5 * (Gt + Gt.transpose(0, 2, 1))
+    t0 = time.perf_counter()
+    O.sigma_tau(Gt, sysm.v, taus=list(range(sample_tau)))
+    t_sig = (time.perf_counter() - t0) / sample_tau * ntau
+    ns = np.arange(sample_freq) * (niw // sample_freq)
+    F = sysm.h
+    t0 = time.perf_counter()
+    G = O.green_iw(-1.0, sysm.S, F, None, sysm.beta, niw, n_idx=ns)
+    _ = float(np.einsum("nij,ji->", G.real, sysm.S))
+    t_dys = (time.perf_counter() - t0) / sample_freq * niw
+    solves = counts["n_eval"] + counts["n_inner"]
+    t_iter = t_sig + t_dys * solves
+    return {
+        "value": 1.0 / t_iter, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"Eq. (Sigma) at {sample_tau} of {ntau} tau points ({t_sig:.1f} s scaled) and "
+                   f"Eq. (GF) at {sample_freq} of {niw} frequencies ({t_dys:.2f} s per full solve) "
+                   f"x {solves} solves per iteration (the GPU iteration's count)"),
+        "seconds_per_iteration": t_iter,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", default="n100", choices=sorted(WORKLOADS))
+    ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3",
+                    help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log("bench.py measures one GPU: this build has no multi-GPU path (the tau axis of "
+            "Eq. (Sigma) would shard across GPUs; see DESIGN.md). Run with --gpus 1.")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic
+    from paper_1405_3273_amd import _lib as L
+    from paper_1405_3273_amd.runtime import Gf2
+
+    gen, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    sysm = getattr(synthetic, gen)()
+    log(f"workload {desc} generated in {time.perf_counter() - t0:.1f} s")
+    g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
+            ntau=sysm.ntau)
+    g.reset(mu0=float(np.mean(np.diag(sysm.h))))
+    prm = L.make_params(prec=args.prec, damp_Sigma=0.5)
+
+    for w in range(args.warmup):
+        r = g.iterate(prm)
+        log(f"warmup {w}: E {r.energy:.10f} inner {r.n_inner} evals {r.n_eval} "
+            f"{r.ms_total:.0f} ms (sigma {r.ms_sigma:.0f})")
+
+    torch.cuda.synchronize()
+    L.gf2_profile_enable(g.ctx, True)
+    reps = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        r = g.iterate(prm)
+        reps.append(r)
+        log(f"step {k}: E {r.energy:.10f} dE {r.dE:.2e} inner {r.n_inner} evals {r.n_eval} "
+            f"{r.ms_total:.0f} ms (sigma {r.ms_sigma:.0f}, fourier {r.ms_fourier:.0f}, "
+            f"inner {r.ms_inner:.0f})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = L.gf2_profile_read(g.ctx)
+    L.gf2_profile_enable(g.ctx, False)
+    steps = args.steps
+    value = steps / elapsed
+
+    # dominant kernel class over the timed region
+    kind = {"sigma_gemm": ("mfma", args.prec), "sigma_splitk": ("mfma", args.prec),
+            "dyson": ("alu", "fp64_vector"), "t2i_expand": ("hbm", "hbm"),
+            "i2t_fold": ("hbm", "hbm"), "fock": ("hbm", "hbm")}
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt, work = prof[dom]
+    bound, pk = kind[dom]
+    avg_s = ms / cnt / 1e3
+    per_launch = work / cnt
+    achieved = per_launch / avg_s
+    unit = "GB/s" if bound == "hbm" else "TFLOP/s"
+    scale = 1e9 if bound == "hbm" else 1e12
+    roofline = {"bound": bound, "achieved": achieved / scale, "peak": PEAK[pk] / scale,
+                "unit": unit, "frac": achieved / PEAK[pk], "traffic": None,
+                "kernel": dom, "launches": cnt, "avg_launch_ms": avg_s * 1e3,
+                "work_per_launch": per_launch}
+    classes = {k: {"ms": v[0], "launches": v[1],
+                   "rate": (v[2] / (v[0] / 1e3) / (1e9 if kind[k][0] == "hbm" else 1e12))
+                   if v[0] > 0 else None,
+                   "rate_unit": "GB/s" if kind[k][0] == "hbm" else "TFLOP/s"}
+               for k, v in prof.items()}
+
+    # stand-alone Sigma(tau) per precision on the current G(tau)
+    sig_rates = {}
+    for pr in [p for p in args.sigma_prec.split(",") if p]:
+        out = torch.empty_like(g.G_tau)
+        g.sigma_tau(g.G_tau, pr, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.sigma_tau(g.G_tau, pr, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        sig_rates[pr] = {"seconds": dt, "tflops_algorithmic": sigma_flops(g.n, sysm.ntau) / dt / 1e12}
+        log(f"sigma {pr}: {dt * 1e3:.1f} ms, {sig_rates[pr]['tflops_algorithmic']:.1f} TFLOP/s")
+
+    counts = {"n_inner": float(np.mean([r.n_inner for r in reps])),
+              "n_eval": float(np.mean([r.n_eval for r in reps]))}
+    line = {
+        "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": desc, "sigma_arithmetic": args.prec,
+                   "other_stages": "f64", "inner_tol_P": prm.tol_P, "damp_Sigma": prm.damp_Sigma,
+                   "mu_search": "illinois", "mix_depth": prm.mix_depth},
+        "roofline": roofline,
+        "kernel_classes": classes,
+        "sigma_tflops": sig_rates,
+        "per_step": {"n_inner": counts["n_inner"], "n_eval": counts["n_eval"],
+                     "ms_sigma": float(np.mean([r.ms_sigma for r in reps])),
+                     "ms_fourier": float(np.mean([r.ms_fourier for r in reps])),
+                     "ms_inner": float(np.mean([r.ms_inner for r in reps])),
+                     "energy": reps[-1].energy, "dE": reps[-1].dE},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(sysm, counts)
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -219,6 +219,32 @@ int gf2_density_fock(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
 int gf2_iterate(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
                 gf2_state *st, gf2_report *rep);
 
+/* ---- opt-in kernel timing -------------------------------------------------
+ * With profiling on, the context brackets every launch of the listed kernel
+ * classes with a pair of HIP events on its stream and records the
+ * algorithmic work of that launch:
+ *   GF2_KC_SIGMA_GEMM    index transforms 1-3 of Eq. (Sigma); work = flops
+ *   GF2_KC_SIGMA_SPLITK  final contraction of Eq. (Sigma);    work = flops
+ *   GF2_KC_DYSON         Eq. (GF) inversions (any mode);       work = flops (8 n^3 per frequency)
+ *   GF2_KC_T2I_EXPAND    Sigma(i w) expansion;                 work = bytes written (16 n^2 niw)
+ *   GF2_KC_I2T_FOLD      G(i w) fold;                          work = bytes read (16 n^2 niw)
+ *   GF2_KC_FOCK          Eq. (FockMatrix);                     work = bytes read (8 n^4)
+ * gf2_profile_enable(ctx, 1) clears the counters and starts recording;
+ * gf2_profile_enable(ctx, 0) stops.  gf2_profile_read synchronises the
+ * stream and fills host arrays [nslots] (nslots <= GF2_KC_COUNT) with the
+ * summed event time (ms), the number of launches and the summed work.
+ */
+#define GF2_KC_SIGMA_GEMM   0
+#define GF2_KC_SIGMA_SPLITK 1
+#define GF2_KC_DYSON        2
+#define GF2_KC_T2I_EXPAND   3
+#define GF2_KC_I2T_FOLD     4
+#define GF2_KC_FOCK         5
+#define GF2_KC_COUNT        6
+
+int gf2_profile_enable(gf2_ctx *ctx, int on);
+int gf2_profile_read(gf2_ctx *ctx, int nslots, double *ms, long long *launches, double *work);
+
 #ifdef __cplusplus
 }
 #endif

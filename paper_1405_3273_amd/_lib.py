@@ -39,7 +39,16 @@ GF2_MU_ILLINOIS = 1
 
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
-            "gf2_iterate")
+            "gf2_iterate", "gf2_profile_enable", "gf2_profile_read")
+
+GF2_KC_SIGMA_GEMM = 0
+GF2_KC_SIGMA_SPLITK = 1
+GF2_KC_DYSON = 2
+GF2_KC_T2I_EXPAND = 3
+GF2_KC_I2T_FOLD = 4
+GF2_KC_FOCK = 5
+GF2_KC_COUNT = 6
+KERNEL_CLASSES = ("sigma_gemm", "sigma_splitk", "dyson", "t2i_expand", "i2t_fold", "fock")
 
 
 class Gf2Error(RuntimeError):
@@ -102,6 +111,8 @@ def load(path: str = None):
                               vp, vp, dp], i),
         "gf2_iterate": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), C.POINTER(gf2_state),
                          C.POINTER(gf2_report)], i),
+        "gf2_profile_enable": ([vp, i], i),
+        "gf2_profile_read": ([vp, i, dp, C.POINTER(C.c_longlong), dp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -201,3 +212,17 @@ def gf2_iterate(ctx, dims: gf2_dims, params: gf2_params, state: gf2_state) -> gf
     rep = gf2_report()
     _check(load().gf2_iterate(ctx, C.byref(dims), C.byref(params), C.byref(state), C.byref(rep)))
     return rep
+
+
+def gf2_profile_enable(ctx, on: bool = True):
+    _check(load().gf2_profile_enable(ctx, 1 if on else 0))
+
+
+def gf2_profile_read(ctx) -> dict:
+    """{class name: (total ms, launches, total work)} for every kernel class."""
+    n = GF2_KC_COUNT
+    ms = (C.c_double * n)()
+    cnt = (C.c_longlong * n)()
+    work = (C.c_double * n)()
+    _check(load().gf2_profile_read(ctx, n, ms, cnt, work))
+    return {KERNEL_CLASSES[k]: (ms[k], int(cnt[k]), work[k]) for k in range(n)}

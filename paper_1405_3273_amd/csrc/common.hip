@@ -49,6 +49,59 @@ void DevBuf::release() {
 }
 
 // ---------------------------------------------------------------------------
+// opt-in kernel timing
+
+static hipEvent_t pool_get(gf2_ctx *c) {
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void prof_resolve(gf2_ctx *c) {
+    for (auto &p : c->prof_pending) {
+        float ms = 0.0f;
+        if (p.start && p.stop && hipEventSynchronize(p.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            c->prof_ms[p.cls] += ms;
+            c->prof_n[p.cls] += 1;
+            c->prof_work[p.cls] += p.work;
+        }
+        if (p.start) c->prof_pool.push_back(p.start);
+        if (p.stop) c->prof_pool.push_back(p.stop);
+    }
+    c->prof_pending.clear();
+}
+
+int prof_begin(gf2_ctx *c, int cls) {
+    if (!c->prof) return -1;
+    if (c->prof_pending.size() >= 8192) prof_resolve(c);
+    gf2_prof_pending p{cls, pool_get(c), pool_get(c), 0.0};
+    if (!p.start || !p.stop) return -1;
+    (void)hipEventRecord(p.start, c->stream);
+    c->prof_pending.push_back(p);
+    return (int)c->prof_pending.size() - 1;
+}
+
+void prof_end(gf2_ctx *c, int handle, double work) {
+    if (handle < 0 || handle >= (int)c->prof_pending.size()) return;
+    auto &p = c->prof_pending[handle];
+    p.work = work;
+    (void)hipEventRecord(p.stop, c->stream);
+}
+
+void prof_release(gf2_ctx *c) {
+    (void)hipStreamSynchronize(c->stream);
+    prof_resolve(c);
+    for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+    c->prof_pool.clear();
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 
 __global__ void k_axpby(size_t n, double a, const double *__restrict__ x, double b,
@@ -266,6 +319,7 @@ int gf2_ctx_destroy(gf2_ctx *c) {
     if (!c) return GF2_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    prof_release(c);
     gf2::DevBuf *bufs[] = {&c->S,        &c->Sinv,      &c->h,       &c->v,        &c->V1_64,
                            &c->W2_64,    &c->V1_32,     &c->W2_32,   &c->sig_T1,   &c->sig_T2,
                            &c->sig_G,    &c->sig_Gb,    &c->sig_part, &c->four_c,  &c->four_C,
@@ -306,6 +360,35 @@ int gf2_set_system(gf2_ctx *c, int n, const double *S, const double *h, const do
     GF2_TRY(sigma_build_layouts(c, true));
     GF2_HIP(hipStreamSynchronize(c->stream));
     c->has_system = true;
+    return GF2_OK;
+}
+
+int gf2_profile_enable(gf2_ctx *c, int on) {
+    if (!c) return fail(GF2_EINVAL, "gf2_profile_enable: ctx is NULL");
+    GF2_HIP(hipSetDevice(c->device));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    prof_resolve(c);
+    if (on) {
+        for (int k = 0; k < GF2_KC_COUNT; ++k) {
+            c->prof_ms[k] = 0.0;
+            c->prof_n[k] = 0;
+            c->prof_work[k] = 0.0;
+        }
+    }
+    c->prof = on != 0;
+    return GF2_OK;
+}
+
+int gf2_profile_read(gf2_ctx *c, int nslots, double *ms, long long *launches, double *work) {
+    if (!c || nslots < 0 || nslots > GF2_KC_COUNT) return fail(GF2_EINVAL, "gf2_profile_read: bad argument");
+    GF2_HIP(hipSetDevice(c->device));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    prof_resolve(c);
+    for (int k = 0; k < nslots; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (launches) launches[k] = c->prof_n[k];
+        if (work) work[k] = c->prof_work[k];
+    }
     return GF2_OK;
 }
 

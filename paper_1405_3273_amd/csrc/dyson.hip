@@ -2,23 +2,20 @@
 // Matsubara frequency, with the reductions the loop needs (FP64).
 //
 // One workgroup inverts one frequency at a time (grid-stride over n).  The
-// matrix lives in registers: a T x T grid of threads, thread (tr, tc) owns
-// rows tr + T a and columns tc + T b (a, b < R, T = ceil(n/R) <= 26, so at
-// most 11 waves per workgroup and ~168 registers per thread; n <= 5*26).  The inverse is an in-place Gauss-Jordan elimination with
-// partial pivoting: step k picks the not-yet-used row r with the largest
-// |Re| + |Im| in column k, scales it and eliminates column k from every
+// matrix lives in registers: thread (tr, tc), tr < 16, tc < TC, owns rows
+// tr + 16 a (a < RA) and columns tc + TC b (b < CB), RA = ceil(n/16).  For
+// n <= 112, TC = 16 and CB = RA (4 waves, one per SIMD); for n <= 160,
+// TC = 32 and CB = ceil(n/32) (8 waves).  Threads are numbered column-major
+// (tid = 16 tc + tr), so the 16 owners of a column sit in 16 consecutive
+// lanes of one wave.
+// The inverse is an in-place Gauss-Jordan elimination with partial pivoting:
+// step k picks the not-yet-used row r with the largest |Re| + |Im| in column
+// k (a 16-lane shuffle argmax), scales it and eliminates column k from every
 // other row.  Rows are never moved; the pivot order r_k is kept, and the
 // physical element (i, j) ends up as G[rinv(i)][r(j)] (rinv = inverse of r).
-// Two barriers per step: after the pivot candidates and column k are
-// published, and after the pivot row is published.
+// Two barriers per step: after column k and the pivot are published, and
+// after the pivot row is published.
 //
-// Reductions (per workgroup, then a fixed-order pass over workgroups):
-//   TRACE:  sum_n Re tr[G_n S]                          -> tr(P S)
-//   FULL:   P_acc += Re G_n + G2 / w_n^2 (LDS, n x n)    -> P
-//   ENERGY: also sum_n Re tr[G_n Sigma_n]                -> E_2b
-// with P = (4/beta) P_acc + G1 - (beta/2) G2,
-//      tr(P S) = (4/beta)(sum Re tr G S + tr(G2 S) sum w^-2) + n - (beta/2) tr(G2 S),
-//      E_2b = (2/beta) sum Re tr[G Sigma] - (2/beta) tr(G1 Sigma_1) (beta/2pi)^2 psi'(niw + 1/2).
 #include "gf2_internal.h"
 
 #include <algorithm>
@@ -27,19 +24,19 @@
 
 namespace gf2 {
 
-constexpr int DY_MAXT = 26;
-constexpr int DY_MAXR = 5;
-constexpr int DY_MAXN = DY_MAXT * DY_MAXR;
-constexpr int DY_THREADS = (DY_MAXT * DY_MAXT + 63) / 64 * 64;   // 704
+constexpr int DY_TR = 16;          // threads per column
+constexpr int DY_MAXN = 160;
+constexpr int DY_MAXTHREADS = 512;
 
 struct DysonArgs {
-    int n, T, niw, mode;
+    int n, niw, mode;
     double beta, mu;
     const double *S, *F, *G2;
     const double2 *Sig;     // may be NULL
     double2 *G;             // may be NULL
     double *partP;          // [gridDim.x][n*n]   (FULL/ENERGY)
     double *parts;          // [gridDim.x][4]     (trace, energy, singular flag)
+    int p_in_lds;           // FULL/ENERGY: accumulate P in LDS (else in partP directly)
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -53,51 +50,50 @@ __device__ __forceinline__ double2 cinv(double2 a) {
     return make_double2(ar / d, -ai / d);
 }
 
-template <int R>
-__global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
-    const int n = a.n, T = a.T;
+template <int RA, int CB, int TC>
+__global__ __launch_bounds__(DY_TR * TC) void k_dyson(DysonArgs a) {
+    const int n = a.n;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int tr = tid / T, tc = tid % T;
-    const bool active = tid < T * T;
+    const int tr = tid & (DY_TR - 1), tc = tid >> 4;
+    const bool active = tc < TC;
+    const int lane = tid & 63;
 
-    __shared__ double2 sh_col[2][DY_MAXN];
-    __shared__ double2 sh_row[DY_MAXN];
-    __shared__ double sh_pv[2][DY_MAXT];
-    __shared__ int sh_pi[2][DY_MAXT];
+    __shared__ double2 sh_col[2][DY_TR * RA];   // padded rows hold zeros
+    __shared__ double2 sh_row[TC * CB];         // padded columns hold zeros
+    __shared__ int sh_r[2];
     __shared__ int perm[DY_MAXN], rinv[DY_MAXN];
-    __shared__ unsigned char pivoted[DY_MAXN];
-    __shared__ double red[2][32];
+    __shared__ double red[2][DY_MAXTHREADS / 64];
     __shared__ int sing;
-    extern __shared__ double shP[];   // n*n when FULL/ENERGY
+    extern __shared__ double shP[];   // n*n when FULL/ENERGY and p_in_lds
 
     const bool full = a.mode != GF2_DYSON_TRACE;
+    double *Pacc = a.p_in_lds ? shP : (a.partP + (size_t)blockIdx.x * n * n);
     if (full)
-        for (int e = tid; e < n * n; e += nthr) shP[e] = 0.0;
+        for (int e = tid; e < n * n; e += nthr) Pacc[e] = 0.0;
     if (tid == 0) sing = 0;
 
     double acc_tr = 0.0, acc_e = 0.0;
-    double mr[R][R], mi[R][R];
+    double mr[RA][CB], mi[RA][CB];
 
     for (int nn = blockIdx.x; nn < a.niw; nn += gridDim.x) {
         const double w = M_PI * (double)(2 * nn + 1) / a.beta;
         const double2 *Sig = a.Sig ? a.Sig + (size_t)nn * n * n : nullptr;
         // The element addresses do not depend on nn; hiding the bases from the
-        // optimiser keeps it from holding 3 R^2 pointers live across the
-        // elimination (they would spill).
+        // optimiser keeps it from holding the pointers live across the elimination.
         const double *Sb = a.S, *Fb = a.F;
         int base = tr * n + tc;
         asm volatile("" : "+s"(Sb), "+s"(Fb), "+v"(base));
         // A = (i w + mu) S - F - Sigma_n
 #pragma unroll
-        for (int ia = 0; ia < R; ++ia)
+        for (int ia = 0; ia < RA; ++ia)
 #pragma unroll
-            for (int jb = 0; jb < R; ++jb) {
-                const int i = tr + T * ia, j = tc + T * jb;
+            for (int jb = 0; jb < CB; ++jb) {
+                const int i = tr + DY_TR * ia, j = tc + TC * jb;
                 mr[ia][jb] = 0.0;
                 mi[ia][jb] = 0.0;
                 if (active && i < n && j < n) {
-                    const int e = base + T * n * ia + T * jb;
+                    const int e = base + DY_TR * n * ia + TC * jb;
                     const double s = Sb[e];
                     double re = a.mu * s - Fb[e], im = w * s;
                     if (Sig) {
@@ -109,104 +105,100 @@ __global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
                     mi[ia][jb] = im;
                 }
             }
-        for (int e = tid; e < n; e += nthr) {
-            pivoted[e] = 0;
-            perm[e] = e;
-            rinv[e] = e;
-        }
-        __syncthreads();
+        unsigned pivmask = 0;   // bit a: row tr + 16 a already used as a pivot
+        __syncthreads();        // previous frequency done with perm / sh_*
 
+        // Each step is the uniform update M[i][j] -= f_i c_j with
+        //   c_j = M[r][j] (j != k), c_k = 1,  M[i][k] preset to 0 (i != r), 1 (i = r),
+        //   f_i = M[i][k]/p (i != r),  f_r = 1 - 1/p,   p = M[r][k],
+        // which leaves exactly the in-place Gauss-Jordan result (row r scaled by
+        // 1/p, column k = -f_i, pivot 1/p) with no per-element special cases.
+        // Padding rows/columns (index >= n) hold zeros and stay zero.
         for (int k = 0; k < n; ++k) {
             const int buf = k & 1;
-            const int kc = k % T, cb = k / T;
+            const int kc = k % TC;
+            const int cb = __builtin_amdgcn_readfirstlane(k / TC);
             if (active && tc == kc) {
                 double best = -1.0;
                 int bi = n;
 #pragma unroll
-                for (int ia = 0; ia < R; ++ia) {
-                    const int i = tr + T * ia;
-                    if (i < n) {
-                        double vr = 0.0, vi = 0.0;
+                for (int jb = 0; jb < CB; ++jb) {
+                    if (jb == cb) {   // scalar branch: cb is wave-uniform
 #pragma unroll
-                        for (int jb = 0; jb < R; ++jb)
-                            if (jb == cb) { vr = mr[ia][jb]; vi = mi[ia][jb]; }
-                        sh_col[buf][i] = make_double2(vr, vi);
-                        if (!pivoted[i]) {
+                        for (int ia = 0; ia < RA; ++ia) {
+                            const int i = tr + DY_TR * ia;
+                            const double vr = mr[ia][jb], vi = mi[ia][jb];
+                            sh_col[buf][i] = make_double2(vr, vi);
                             const double mag = fabs(vr) + fabs(vi);
-                            if (mag > best) { best = mag; bi = i; }
+                            const bool cand = !((pivmask >> ia) & 1u) && mag > best;
+                            best = cand ? mag : best;
+                            bi = cand ? i : bi;
+                            mr[ia][jb] = 0.0;   // preset column k (row r gets 1 below)
+                            mi[ia][jb] = 0.0;
                         }
                     }
                 }
-                sh_pv[buf][tr] = best;
-                sh_pi[buf][tr] = bi;
+                // argmax over the 16 owners (consecutive lanes); ties -> smaller row
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 16);
+                    const int oi = __shfl_xor(bi, off, 16);
+                    const bool take = ob > best || (ob == best && oi < bi);
+                    best = take ? ob : best;
+                    bi = take ? oi : bi;
+                }
+                if (tr == 0) sh_r[buf] = (best > 0.0 && bi < n) ? bi : -1;
             }
             __syncthreads();
-            double best = -1.0;
-            int r = n;
-            for (int t = 0; t < T; ++t) {
-                const double pv = sh_pv[buf][t];
-                const int pi = sh_pi[buf][t];
-                if (pv > best || (pv == best && pi < r)) { best = pv; r = pi; }
-            }
-            if (!(best > 0.0) || r >= n) {
-                // singular (or NaN) matrix: flag and stop this frequency
+            int r = sh_r[buf];
+            if (r < 0) {
+                // singular (or NaN) matrix: flag, continue with a valid index
                 if (tid == 0) sing = 1;
-                r = (r >= n) ? 0 : r;
+                r = k;
             }
-            if (active && tr == r % T) {
-                const int ar = r / T;
+            const int rr = r & (DY_TR - 1);
+            const int ra = __builtin_amdgcn_readfirstlane(r >> 4);
+            // the pivot is already published with column k: invert it while the
+            // row owners publish row r
+            const double2 ipiv = cinv(sh_col[buf][r]);
+            if (active && tr == rr) {
+                pivmask |= 1u << ra;
 #pragma unroll
-                for (int jb = 0; jb < R; ++jb) {
-                    const int j = tc + T * jb;
-                    if (j < n) {
-                        double vr = 0.0, vi = 0.0;
+                for (int ia = 0; ia < RA; ++ia) {
+                    if (ia == ra) {   // scalar branch
 #pragma unroll
-                        for (int ia = 0; ia < R; ++ia)
-                            if (ia == ar) { vr = mr[ia][jb]; vi = mi[ia][jb]; }
-                        sh_row[j] = make_double2(vr, vi);
+                        for (int jb = 0; jb < CB; ++jb) {
+                            const int j = tc + TC * jb;
+                            if (jb == cb && tc == kc) mr[ia][jb] = 1.0;
+                            sh_row[j] = make_double2(mr[ia][jb], mi[ia][jb]);
+                        }
                     }
                 }
             }
             if (tid == 0) {
-                pivoted[r] = 1;
                 perm[k] = r;
                 rinv[r] = k;
             }
             __syncthreads();
             if (active) {
-                const double2 ipiv = cinv(sh_row[k]);
-                double2 crow[R];
+                double2 crow[CB];
 #pragma unroll
-                for (int jb = 0; jb < R; ++jb) {
-                    const int j = tc + T * jb;
-                    crow[jb] = (j < n) ? sh_row[j] : make_double2(0.0, 0.0);
-                }
+                for (int jb = 0; jb < CB; ++jb) crow[jb] = sh_row[tc + TC * jb];
 #pragma unroll
-                for (int ia = 0; ia < R; ++ia) {
-                    const int i = tr + T * ia;
-                    if (i >= n) continue;
-                    if (i == r) {
+                for (int ia = 0; ia < RA; ++ia) {
+                    const int i = tr + DY_TR * ia;
+                    const double2 cv = sh_col[buf][i];
+                    double fx = cv.x * ipiv.x - cv.y * ipiv.y;
+                    double fy = cv.x * ipiv.y + cv.y * ipiv.x;
+                    const bool is_r = (i == r);
+                    fx = is_r ? 1.0 - ipiv.x : fx;
+                    fy = is_r ? -ipiv.y : fy;
 #pragma unroll
-                        for (int jb = 0; jb < R; ++jb) {
-                            const int j = tc + T * jb;
-                            const double2 v = (j == k) ? ipiv : cmul(crow[jb], ipiv);
-                            mr[ia][jb] = v.x;
-                            mi[ia][jb] = v.y;
-                        }
-                    } else {
-                        const double2 f = cmul(sh_col[buf][i], ipiv);
-#pragma unroll
-                        for (int jb = 0; jb < R; ++jb) {
-                            const int j = tc + T * jb;
-                            if (j == k) {
-                                mr[ia][jb] = -f.x;
-                                mi[ia][jb] = -f.y;
-                            } else {
-                                // M -= f * crow
-                                mr[ia][jb] -= f.x * crow[jb].x - f.y * crow[jb].y;
-                                mi[ia][jb] -= f.x * crow[jb].y + f.y * crow[jb].x;
-                            }
-                        }
+                    for (int jb = 0; jb < CB; ++jb) {
+                        mr[ia][jb] = fma(-fx, crow[jb].x, mr[ia][jb]);
+                        mr[ia][jb] = fma(fy, crow[jb].y, mr[ia][jb]);
+                        mi[ia][jb] = fma(-fx, crow[jb].y, mi[ia][jb]);
+                        mi[ia][jb] = fma(-fy, crow[jb].x, mi[ia][jb]);
                     }
                 }
             }
@@ -216,17 +208,17 @@ __global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
         // physical (i, j) holds G[rinv(i)][perm(j)]
         const double iw2 = 1.0 / (w * w);
 #pragma unroll
-        for (int ia = 0; ia < R; ++ia)
+        for (int ia = 0; ia < RA; ++ia)
 #pragma unroll
-            for (int jb = 0; jb < R; ++jb) {
-                const int i = tr + T * ia, j = tc + T * jb;
+            for (int jb = 0; jb < CB; ++jb) {
+                const int i = tr + DY_TR * ia, j = tc + TC * jb;
                 if (!(active && i < n && j < n)) continue;
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
                 if (!full) {
                     acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
                 } else {
-                    shP[e] += mr[ia][jb] + a.G2[e] * iw2;
+                    Pacc[e] += mr[ia][jb] + a.G2[e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
                     if (a.mode == GF2_DYSON_ENERGY && Sig) {
                         const double2 sg = Sig[(size_t)gb * n + ga];
@@ -234,8 +226,8 @@ __global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
                     }
                 }
             }
-        __syncthreads();   // shP / perm reuse by the next frequency
     }
+    __syncthreads();
 
     // block reductions (fixed order)
     {
@@ -245,7 +237,7 @@ __global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
             v1 += __shfl_down(v1, off);
         }
         const int wv = tid >> 6;
-        if ((tid & 63) == 0) {
+        if (lane == 0) {
             red[0][wv] = v0;
             red[1][wv] = v1;
         }
@@ -264,7 +256,7 @@ __global__ __launch_bounds__(DY_THREADS) void k_dyson(DysonArgs a) {
             ps[3] = 0.0;
         }
     }
-    if (full)
+    if (full && a.p_in_lds)
         for (int e = tid; e < n * n; e += nthr) a.partP[(size_t)blockIdx.x * n * n + e] = shP[e];
 }
 
@@ -314,12 +306,12 @@ __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict
     if (t < 5) out[t] = sh[t][0];
 }
 
-template <int R>
-static int launch_dyson(dim3 grid, dim3 block, size_t shm, hipStream_t s, const DysonArgs &a) {
+template <int RA, int CB, int TC>
+static int launch_dyson(dim3 grid, size_t shm, hipStream_t s, const DysonArgs &a) {
     if (shm > 0)
-        GF2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dyson<R>),
+        GF2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dyson<RA, CB, TC>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL(k_dyson<R>, grid, block, shm, s, a);
+    hipLaunchKernelGGL((k_dyson<RA, CB, TC>), grid, dim3(DY_TR * TC), shm, s, a);
     return GF2_OK;
 }
 
@@ -349,12 +341,15 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
               double *mom_out, double *out) {
     const int n = c->n, niw = d->niw;
     const size_t ne = (size_t)n * n;
-    if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 130 is not supported yet");
-    const int R = (n + DY_MAXT - 1) / DY_MAXT;
-    const int T = (n + R - 1) / R;
-    const int nthr = (T * T + 63) / 64 * 64;   // whole waves: the shuffles need full waves
-    const int nblocks = std::min(niw, 512);
+    if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
+    const int RA = (n + DY_TR - 1) / DY_TR;
     const bool full = mode != GF2_DYSON_TRACE;
+    const bool p_in_lds = full && ne * 8 <= 96 * 1024;
+    const size_t shm = p_in_lds ? ne * 8 : 0;
+    int dev_cus = 256;
+    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    // two resident workgroups per CU give each one a partner to overlap barriers with
+    const int nblocks = std::max(1, std::min(niw, 2 * dev_cus));
 
     GF2_TRY(c->dys_X.ensure(6 * ne * 8));
     GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
@@ -365,21 +360,28 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     GF2_TRY(moments(c, mu, F, (mode == GF2_DYSON_TRACE) ? nullptr : Sig1, mom, scr));
 
     DysonArgs a{};
-    a.n = n; a.T = T; a.niw = niw; a.mode = mode;
+    a.n = n; a.niw = niw; a.mode = mode;
     a.beta = d->beta; a.mu = mu;
     a.S = c->S.as<double>(); a.F = F; a.G2 = mom + ne;
     a.Sig = Sig_iw; a.G = full ? G_iw : nullptr;
     a.partP = full ? c->dys_part.as<double>() : nullptr;
     a.parts = c->dys_aux.as<double>();
-    const size_t shm = full ? ne * 8 : 0;
-    dim3 grid(nblocks), block(nthr);
-    switch (R) {
-        case 1: GF2_TRY(launch_dyson<1>(grid, block, shm, c->stream, a)); break;
-        case 2: GF2_TRY(launch_dyson<2>(grid, block, shm, c->stream, a)); break;
-        case 3: GF2_TRY(launch_dyson<3>(grid, block, shm, c->stream, a)); break;
-        case 4: GF2_TRY(launch_dyson<4>(grid, block, shm, c->stream, a)); break;
-        default: GF2_TRY(launch_dyson<5>(grid, block, shm, c->stream, a)); break;
+    a.p_in_lds = p_in_lds ? 1 : 0;
+    dim3 grid(nblocks);
+    const int ph = prof_begin(c, GF2_KC_DYSON);
+    switch (RA) {
+        case 1: GF2_TRY((launch_dyson<1, 1, 16>(grid, shm, c->stream, a))); break;
+        case 2: GF2_TRY((launch_dyson<2, 2, 16>(grid, shm, c->stream, a))); break;
+        case 3: GF2_TRY((launch_dyson<3, 3, 16>(grid, shm, c->stream, a))); break;
+        case 4: GF2_TRY((launch_dyson<4, 4, 16>(grid, shm, c->stream, a))); break;
+        case 5: GF2_TRY((launch_dyson<5, 5, 16>(grid, shm, c->stream, a))); break;
+        case 6: GF2_TRY((launch_dyson<6, 6, 16>(grid, shm, c->stream, a))); break;
+        case 7: GF2_TRY((launch_dyson<7, 7, 16>(grid, shm, c->stream, a))); break;
+        case 8: GF2_TRY((launch_dyson<8, 4, 32>(grid, shm, c->stream, a))); break;
+        case 9: GF2_TRY((launch_dyson<9, 5, 32>(grid, shm, c->stream, a))); break;
+        default: GF2_TRY((launch_dyson<10, 5, 32>(grid, shm, c->stream, a))); break;
     }
+    prof_end(c, ph, 8.0 * (double)n * n * n * niw);
     GF2_HIP(hipGetLastError());
 
     double *dout = c->dys_out.as<double>();

@@ -71,8 +71,10 @@ int fock_run(gf2_ctx *c, const double *P, double *F) {
     GF2_TRY(c->fock_part.ensure((FK_ASPLIT + 1) * n2 * 8));
     double *J = c->fock_part.as<double>();
     double *Kp = J + n2;
+    const int ph = prof_begin(c, GF2_KC_FOCK);
     hipLaunchKernelGGL(k_fock_jk, dim3(n, FK_ASPLIT), dim3(FK_THREADS), 0, c->stream, n,
                        c->v.as<double>(), P, J, Kp);
+    prof_end(c, ph, 8.0 * (double)n2 * n2);
     // every slice writes its K partial (zero for an empty a-range)
     hipLaunchKernelGGL(k_fock_sum, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, c->stream, n,
                        FK_ASPLIT, c->h.as<double>(), J, Kp, F);

@@ -240,8 +240,10 @@ int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2
     GemmArgsF64 g{tw, 2LL * M, coef, 4LL * ne, Cm, 4LL * ne, 2 * M, 4 * ne, M, 1.0};
     GF2_TRY(gemm_f64_kmajor(c, g));
     const int nr = std::min(M, niw);
+    const int ph = prof_begin(c, GF2_KC_T2I_EXPAND);
     hipLaunchKernelGGL(k_expand, dim3((ne + 255) / 256, nr), dim3(256), 0, c->stream, ne, M, niw,
                        Cm, tab, Sig_iw);
+    prof_end(c, ph, 16.0 * (double)ne * niw);
     if (Sig1)
         hipLaunchKernelGGL(k_moment1, dim3((ne + 255) / 256), dim3(256), 0, c->stream, ne, M,
                            Sig_tau, Sig1);
@@ -294,8 +296,10 @@ int fourier_iw2tau(gf2_ctx *c, const gf2_dims *d, const double2 *G_iw, const dou
     double *Fre = c->four_fold.as<double>();
     double *Fim = Fre + (size_t)M * ne;
     double *tw = Fre + (size_t)2 * M * ne;
+    const int ph = prof_begin(c, GF2_KC_I2T_FOLD);
     hipLaunchKernelGGL(k_fold, dim3((ne + 255) / 256, M), dim3(256), 0, c->stream, ne, M, niw,
                        d->beta, G_iw, mom, Fre, Fim);
+    prof_end(c, ph, 16.0 * (double)ne * niw);
     {
         const long long tot = 2LL * M * (M + 1);
         const unsigned blocks = (unsigned)std::min<long long>((tot + 255) / 256, 8192);

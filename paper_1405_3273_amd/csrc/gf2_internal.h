@@ -44,9 +44,23 @@ enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2 };
 
 }  // namespace gf2
 
+struct gf2_prof_pending {
+    int cls;
+    hipEvent_t start, stop;
+    double work;
+};
+
 struct gf2_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+
+    // ---- opt-in kernel timing ----
+    bool prof = false;
+    double prof_ms[GF2_KC_COUNT] = {0};
+    long long prof_n[GF2_KC_COUNT] = {0};
+    double prof_work[GF2_KC_COUNT] = {0};
+    std::vector<gf2_prof_pending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
 
     // ---- system (gf2_set_system) ----
     int n = 0;
@@ -71,6 +85,13 @@ struct gf2_ctx {
 };
 
 namespace gf2 {
+
+// ---- opt-in kernel timing (common.hip) ----------------------------------------
+// prof_begin records a start event for class cls (returns a handle, -1 when
+// profiling is off); prof_end records the stop event and the launch's work.
+int prof_begin(gf2_ctx *c, int cls);
+void prof_end(gf2_ctx *c, int handle, double work);
+void prof_release(gf2_ctx *c);
 
 // ---- small shared kernels (common.hip) ---------------------------------------
 int copy_d2d(gf2_ctx *c, void *dst, const void *src, size_t bytes);

@@ -598,21 +598,28 @@ int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, doub
         g.ldc = N;
         g.sB = N2;
         g.sC = N4;
+        const double stage_flops = 2.0 * (double)N4 * (double)N * nb;
         // S1: T1 = V1^T A   (A = G(tau))
         g.A = V1; g.sA = 0;
         g.B = c->sig_G.ptr;
         g.C = c->sig_T1.ptr;
+        int ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
         GF2_TRY(gemm(c, mode, true, g, nb));
+        prof_end(c, ph, stage_flops);
         // S2: T2 = T1 x_q B   (B = G(-tau))
         g.A = c->sig_T1.ptr; g.sA = N4;
         g.B = c->sig_Gb.ptr;
         g.C = c->sig_T2.ptr;
+        ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
         GF2_TRY(gemm(c, mode, true, g, nb));
+        prof_end(c, ph, stage_flops);
         // S3: X = T2 x_k A  (into T1)
         g.A = c->sig_T2.ptr; g.sA = N4;
         g.B = c->sig_G.ptr;
         g.C = c->sig_T1.ptr;
+        ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
         GF2_TRY(gemm(c, mode, true, g, nb));
+        prof_end(c, ph, stage_flops);
         // S4: partial[z] = -X[(t,i)][K-slice z] W2[K-slice z][j]
         GemmArgs h{};
         h.A = c->sig_T1.ptr;
@@ -631,7 +638,9 @@ int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, doub
         h.split = 1;
         h.alpha = -1.0;
         h.vecA = vec ? 1 : 0;
+        ph = prof_begin(c, GF2_KC_SIGMA_SPLITK);
         GF2_TRY(gemm(c, mode, false, h, nsplit));
+        prof_end(c, ph, stage_flops);
         {
             const size_t tot = (size_t)nb * N2;
             const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
