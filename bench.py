@@ -180,7 +180,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "sigma_arithmetic": args.prec,
                    "other_stages": "f64", "inner_tol_P": prm.tol_P, "damp_Sigma": prm.damp_Sigma,
-                   "mu_search": "illinois", "mix_depth": prm.mix_depth},
+                   "mu_search": "secant", "mix_depth": prm.mix_depth},
         "roofline": roofline,
         "kernel_classes": classes,
         "sigma_tflops": sig_rates,

@@ -67,8 +67,10 @@ extern "C" {
 #define GF2_DYSON_FULL   1   /* + G(i w) (optional) and P                        */
 #define GF2_DYSON_ENERGY 2   /* + the two-body Galitskii-Migdal energy            */
 
-#define GF2_MU_BISECT    0
-#define GF2_MU_ILLINOIS  1
+#define GF2_MU_BISECT    0   /* bracket around mu0, midpoints                    */
+#define GF2_MU_ILLINOIS  1   /* bracket around mu0, Illinois regula falsi         */
+#define GF2_MU_SECANT    2   /* start at mu0, secant step from the previous slope, */
+                             /* expand to a bracket, then Illinois                */
 
 typedef struct gf2_ctx gf2_ctx;
 
@@ -91,7 +93,7 @@ typedef struct {
     double damp_P;       /* density damping a_P in the inner loop              */
     int    mix_depth;    /* Pulay history length (1 = plain damping)           */
     double damp_Sigma;   /* Sigma(tau) damping a_S in the outer loop           */
-    int    mu_method;    /* GF2_MU_BISECT or GF2_MU_ILLINOIS                   */
+    int    mu_method;    /* GF2_MU_BISECT, GF2_MU_ILLINOIS or GF2_MU_SECANT    */
     int    prec;         /* GF2_PREC_* for Sigma(tau)                          */
 } gf2_params;
 

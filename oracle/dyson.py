@@ -31,6 +31,14 @@ regula-falsi point (``method='illinois'``: the secant through the two
 ends, with the function value kept at an end that survives two steps in
 a row halved; the midpoint is used whenever the secant point is not
 strictly inside the bracket).
+
+``method='secant'`` builds the bracket from the previous mu instead: it
+evaluates N at mu0 first (accepting it when |N - N_e| < tol_N), then steps
+by -f(mu0)/slope, where slope is dN/dmu from the previous search (or
+1/hw without one), clamped to [4 tol_mu, hw] in size, and doubles the step
+while the sign does not change; the bracket found is then closed by the
+Illinois iteration above.  It returns the secant slope of the final
+bracket for the next search.
 """
 import numpy as np
 
@@ -84,51 +92,86 @@ def particle_number(mu, S, F, Sigma_iw, Sigma1, beta, niw):
 
 
 def find_mu(nelec, S, F, Sigma_iw, Sigma1, beta, niw, mu0=0.0, *, halfwidth=0.5,
-            tol_mu=1e-12, tol_N=1e-10, max_steps=200, method="illinois"):
-    """Bracketing search for mu with tr(P(mu) S) = nelec.  Returns (mu, evaluations)."""
+            tol_mu=1e-12, tol_N=1e-10, max_steps=200, method="illinois", slope=None,
+            return_slope=False):
+    """Bracketing search for mu with tr(P(mu) S) = nelec.
+
+    Returns (mu, evaluations), or (mu, evaluations, slope) with return_slope.
+    """
     n = S.shape[0]
     if nelec < 0 or nelec > 2 * n:
         raise BracketError(f"nelec={nelec} outside [0, {2 * n}]")
-    if method not in ("bisect", "illinois"):
+    if method not in ("bisect", "illinois", "secant"):
         raise ValueError(method)
 
     def f(mu):
         return particle_number(mu, S, F, Sigma_iw, Sigma1, beta, niw) - nelec
 
+    def done(mu, ev, lo=None, f_lo=None, hi=None, f_hi=None):
+        sl = slope
+        if lo is not None and hi is not None and hi > lo and f_hi > f_lo:
+            sl = (f_hi - f_lo) / (hi - lo)
+        return (mu, ev, sl) if return_slope else (mu, ev)
+
     evals = 0
-    lo, hi = mu0 - halfwidth, mu0 + halfwidth
-    f_lo = f(lo); evals += 1
-    while f_lo > 0.0:
-        if evals > max_steps:
-            raise BracketError("lower end of the mu bracket not found")
-        lo, hi = lo - (hi - lo), lo
+    if method == "secant":
+        a = mu0
+        fa = f(a); evals += 1
+        if abs(fa) < tol_N:
+            return done(a, evals)
+        s_ = slope if (slope is not None and slope > 0.0) else 1.0 / halfwidth
+        step = -fa / s_
+        mag = min(max(abs(step), 4.0 * tol_mu), halfwidth)
+        step = mag if step > 0.0 else -mag
+        b = a + step
+        while True:
+            if evals > max_steps:
+                raise BracketError("mu bracket not found")
+            fb = f(b); evals += 1
+            if abs(fb) < tol_N:
+                lo, flo, hi, fhi = (a, fa, b, fb) if a < b else (b, fb, a, fa)
+                return done(b, evals, lo, flo, hi, fhi)
+            if (fb > 0.0) != (fa > 0.0):
+                break
+            a, fa, b = b, fb, b + 2.0 * (b - a)
+        lo, f_lo, hi, f_hi = (a, fa, b, fb) if a < b else (b, fb, a, fa)
+    else:
+        lo, hi = mu0 - halfwidth, mu0 + halfwidth
         f_lo = f(lo); evals += 1
-    f_hi = f(hi); evals += 1
-    while f_hi < 0.0:
-        if evals > max_steps:
-            raise BracketError("upper end of the mu bracket not found")
-        lo, hi = hi, hi + (hi - lo)
+        while f_lo > 0.0:
+            if evals > max_steps:
+                raise BracketError("lower end of the mu bracket not found")
+            lo, hi = lo - (hi - lo), lo
+            f_lo = f(lo); evals += 1
         f_hi = f(hi); evals += 1
+        while f_hi < 0.0:
+            if evals > max_steps:
+                raise BracketError("upper end of the mu bracket not found")
+            lo, hi = hi, hi + (hi - lo)
+            f_hi = f(hi); evals += 1
+    t_lo, t_hi = f_lo, f_hi          # true values at the bracket ends
     side = 0
     for _ in range(max_steps):
         mid = 0.5 * (lo + hi)
-        if method == "illinois" and f_hi > f_lo:
+        if method != "bisect" and f_hi > f_lo:
             x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo)
             if lo < x < hi:
                 mid = x
         fm = f(mid); evals += 1
         if abs(fm) < tol_N:
-            return mid, evals
+            if fm < 0.0:
+                return done(mid, evals, mid, fm, hi, t_hi)
+            return done(mid, evals, lo, t_lo, mid, fm)
         if fm < 0.0:
-            lo, f_lo = mid, fm
+            lo, f_lo, t_lo = mid, fm, fm
             if side == -1:
                 f_hi *= 0.5
             side = -1
         else:
-            hi, f_hi = mid, fm
+            hi, f_hi, t_hi = mid, fm, fm
             if side == 1:
                 f_lo *= 0.5
             side = 1
         if hi - lo < tol_mu:
-            return 0.5 * (lo + hi), evals
+            return done(0.5 * (lo + hi), evals, lo, t_lo, hi, t_hi)
     raise NoConvergence("mu search did not converge")

@@ -17,6 +17,8 @@ algorithm"):
 
 Readings for what the paper leaves open (tolerances and order):
 
+* the mu search of each pass starts from the previous pass's mu and slope
+  dN/dmu (the first pass of an outer iteration has no slope);
 * one inner pass: F = F(P_in) -> mu search at that F -> Dyson solve at
   that mu -> P_out; the residual is r = P_out - P_in and the inner loop
   stops when max|r| < tol_P.  The next input density is the damped
@@ -62,7 +64,7 @@ class Params:
     damp_P: float = 0.3
     mix_depth: int = 8
     damp_Sigma: float = 0.0
-    mu_method: str = "illinois"
+    mu_method: str = "secant"
 
 
 @dataclass
@@ -154,11 +156,12 @@ def inner_loop(sysm, params: Params, F, P_in, mu0, Sigma_iw, Sigma1):
     mu = mu0
     n_eval = 0
     hist = []
+    slope = None
     for it in range(1, params.max_inner + 1):
-        mu, ne = find_mu(sysm.nelec, S, F, Sigma_iw, Sigma1, beta, niw, mu,
-                         halfwidth=params.mu_halfwidth, tol_mu=params.tol_mu,
-                         tol_N=params.tol_N, max_steps=params.max_bisect,
-                         method=params.mu_method)
+        mu, ne, slope = find_mu(sysm.nelec, S, F, Sigma_iw, Sigma1, beta, niw, mu,
+                                halfwidth=params.mu_halfwidth, tol_mu=params.tol_mu,
+                                tol_N=params.tol_N, max_steps=params.max_bisect,
+                                method=params.mu_method, slope=slope, return_slope=True)
         n_eval += ne
         G = green_iw(mu, S, F, Sigma_iw, beta, niw)
         mom = tail_moments(S, F, mu, Sigma1)

@@ -36,6 +36,7 @@ GF2_DYSON_ENERGY = 2
 
 GF2_MU_BISECT = 0
 GF2_MU_ILLINOIS = 1
+GF2_MU_SECANT = 2
 
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
@@ -146,8 +147,8 @@ def make_dims(n, nelec, ntau, niw, beta) -> gf2_dims:
 
 def make_params(tol_mu=1e-12, tol_N=1e-10, tol_P=1e-10, tol_E=1e-11, max_inner=100,
                 max_bisect=200, mu_halfwidth=0.5, damp_P=0.3, mix_depth=8, damp_Sigma=0.0,
-                mu_method="illinois", prec="fp32") -> gf2_params:
-    mm = {"bisect": GF2_MU_BISECT, "illinois": GF2_MU_ILLINOIS}[mu_method]
+                mu_method="secant", prec="fp32") -> gf2_params:
+    mm = {"bisect": GF2_MU_BISECT, "illinois": GF2_MU_ILLINOIS, "secant": GF2_MU_SECANT}[mu_method]
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     return gf2_params(tol_mu, tol_N, tol_P, tol_E, max_inner, max_bisect, mu_halfwidth, damp_P,
                       mix_depth, damp_Sigma, mm, pr)

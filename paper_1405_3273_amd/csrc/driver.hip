@@ -5,11 +5,14 @@
 //
 // mu search (step 2.a): bracketing search on N(mu) = tr(P(mu) S) - nelec.
 //   Bracket [mu0 - hw, mu0 + hw]; while N(lo) > 0 move to [lo - w, lo], while
-//   N(hi) < 0 move to [hi, hi + w]; then evaluate an interior point (midpoint,
-//   or the Illinois regula-falsi point when it is strictly inside), accept it
-//   when |N| < tol_N, otherwise replace the end with the same sign (Illinois
-//   halves the value kept at an end that survives two steps in a row); stop
-//   at bracket width < tol_mu with the midpoint.
+//   N(hi) < 0 move to [hi, hi + w]; or (secant start) evaluate N(mu0), step by
+//   -N(mu0)/slope (slope from the previous search, 1/hw without one; step size
+//   clamped to [4 tol_mu, hw]) and double the step until the sign changes.
+//   Then evaluate an interior point (midpoint, or the Illinois regula-falsi
+//   point when it is strictly inside), accept it when |N| < tol_N, otherwise
+//   replace the end with the same sign (Illinois halves the value kept at an
+//   end that survives two steps in a row); stop at bracket width < tol_mu with
+//   the midpoint.
 // Inner loop (2.a-2.b): F = F(P_in) -> mu -> P_out; r = P_out - P_in; stop at
 //   max|r| < tol_P; next P_in = sum_a c_a (x_a + (1 - a_P) r_a) with
 //   c = argmin |sum c_a r_a|, sum c_a = 1 over the last mix_depth pairs.
@@ -37,38 +40,77 @@ static int particle_excess(gf2_ctx *c, const gf2_dims *d, double mu, const doubl
     return GF2_OK;
 }
 
+// Returns mu and the number of evaluations; *slope is read (hint, <= 0 = none)
+// and replaced by the secant slope dN/dmu of the final bracket when known.
 static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
-                   const double2 *Sig, double mu0, double *mu_out, int *evals_out) {
+                   const double2 *Sig, double mu0, double *mu_out, int *evals_out,
+                   double *slope) {
     const int n = c->n;
     if (d->nelec < 0 || d->nelec > 2 * n)
         return fail(GF2_EBRACKET, "mu search: nelec outside [0, 2n]");
     int evals = 0;
-    double lo = mu0 - p->mu_halfwidth, hi = mu0 + p->mu_halfwidth;
-    double f_lo, f_hi;
-    GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
-    ++evals;
-    while (f_lo > 0.0) {
-        if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no lower bracket end");
-        const double w = hi - lo;
-        hi = lo;
-        lo = lo - w;
+    double lo, hi, f_lo, f_hi;
+    auto finish = [&](double mu, double l, double fl, double h, double fh, bool have) {
+        if (have && h > l && fh > fl && slope) *slope = (fh - fl) / (h - l);
+        *mu_out = mu;
+        *evals_out = evals;
+        return GF2_OK;
+    };
+    if (p->mu_method == GF2_MU_SECANT) {
+        double a = mu0, fa, fb;
+        GF2_TRY(particle_excess(c, d, a, F, Sig, &fa));
+        ++evals;
+        if (std::fabs(fa) < p->tol_N) return finish(a, 0, 0, 0, 0, false);
+        const double s_ = (slope && *slope > 0.0) ? *slope : 1.0 / p->mu_halfwidth;
+        double step = -fa / s_;
+        const double mag = std::fmin(std::fmax(std::fabs(step), 4.0 * p->tol_mu), p->mu_halfwidth);
+        step = step > 0.0 ? mag : -mag;
+        double b = a + step;
+        for (;;) {
+            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no bracket found");
+            GF2_TRY(particle_excess(c, d, b, F, Sig, &fb));
+            ++evals;
+            if (std::fabs(fb) < p->tol_N) {
+                if (a < b) return finish(b, a, fa, b, fb, true);
+                return finish(b, b, fb, a, fa, true);
+            }
+            if ((fb > 0.0) != (fa > 0.0)) break;
+            const double nb = b + 2.0 * (b - a);
+            a = b;
+            fa = fb;
+            b = nb;
+        }
+        if (a < b) { lo = a; f_lo = fa; hi = b; f_hi = fb; }
+        else       { lo = b; f_lo = fb; hi = a; f_hi = fa; }
+    } else {
+        lo = mu0 - p->mu_halfwidth;
+        hi = mu0 + p->mu_halfwidth;
         GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
         ++evals;
-    }
-    GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
-    ++evals;
-    while (f_hi < 0.0) {
-        if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no upper bracket end");
-        const double w = hi - lo;
-        lo = hi;
-        hi = hi + w;
+        while (f_lo > 0.0) {
+            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no lower bracket end");
+            const double w = hi - lo;
+            hi = lo;
+            lo = lo - w;
+            GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
+            ++evals;
+        }
         GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
         ++evals;
+        while (f_hi < 0.0) {
+            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no upper bracket end");
+            const double w = hi - lo;
+            lo = hi;
+            hi = hi + w;
+            GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
+            ++evals;
+        }
     }
+    double t_lo = f_lo, t_hi = f_hi;   // true values at the bracket ends
     int side = 0;
     for (int step = 0; step < p->max_bisect; ++step) {
         double mid = 0.5 * (lo + hi);
-        if (p->mu_method == GF2_MU_ILLINOIS && f_hi > f_lo) {
+        if (p->mu_method != GF2_MU_BISECT && f_hi > f_lo) {
             const double x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
             if (lo < x && x < hi) mid = x;
         }
@@ -76,26 +118,23 @@ static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const dou
         GF2_TRY(particle_excess(c, d, mid, F, Sig, &fm));
         ++evals;
         if (std::fabs(fm) < p->tol_N) {
-            *mu_out = mid;
-            *evals_out = evals;
-            return GF2_OK;
+            if (fm < 0.0) return finish(mid, mid, fm, hi, t_hi, true);
+            return finish(mid, lo, t_lo, mid, fm, true);
         }
         if (fm < 0.0) {
             lo = mid;
             f_lo = fm;
+            t_lo = fm;
             if (side == -1) f_hi *= 0.5;
             side = -1;
         } else {
             hi = mid;
             f_hi = fm;
+            t_hi = fm;
             if (side == 1) f_lo *= 0.5;
             side = 1;
         }
-        if (hi - lo < p->tol_mu) {
-            *mu_out = 0.5 * (lo + hi);
-            *evals_out = evals;
-            return GF2_OK;
-        }
+        if (hi - lo < p->tol_mu) return finish(0.5 * (lo + hi), lo, t_lo, hi, t_hi, true);
     }
     return fail(GF2_ENOCONV, "mu search did not converge");
 }
@@ -103,8 +142,9 @@ static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const dou
 // One pass of 2.a-2.b without the Fock rebuild: mu, P_out, G(i w), moments, E_2b.
 static int density_pass(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
                         const double2 *Sig, const double *Sig1, double *mu, double *P_out,
-                        double2 *G_iw, double *mom, double *trPS, double *e2b, int *evals) {
-    GF2_TRY(find_mu(c, d, p, F, Sig, *mu, mu, evals));
+                        double2 *G_iw, double *mom, double *trPS, double *e2b, int *evals,
+                        double *slope) {
+    GF2_TRY(find_mu(c, d, p, F, Sig, *mu, mu, evals, slope));
     double r[2];
     const int mode = Sig ? GF2_DYSON_ENERGY : GF2_DYSON_FULL;
     GF2_TRY(dyson_run(c, d, mode, *mu, F, Sig, Sig1, G_iw, P_out, mom, r));
@@ -227,7 +267,8 @@ static int check_params(const gf2_params *p, const char *who) {
     if (!(p->tol_mu > 0) || !(p->tol_N > 0) || !(p->tol_P > 0) || p->max_inner < 1 ||
         p->max_bisect < 1 || !(p->mu_halfwidth > 0) || p->mix_depth < 1 || p->mix_depth > 32 ||
         !(p->damp_P >= 0 && p->damp_P < 1) || !(p->damp_Sigma >= 0 && p->damp_Sigma < 1) ||
-        (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS) ||
+        (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS &&
+         p->mu_method != GF2_MU_SECANT) ||
         p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16X3)
         return fail(GF2_EINVAL, std::string(who) + ": bad parameters");
     return GF2_OK;
@@ -251,9 +292,10 @@ extern "C" int gf2_density_fock(gf2_ctx *c, const gf2_dims *d, const gf2_params 
     double trPS = 0, e2b = 0;
     int evals = 0;
     double mu = *mu_inout;
+    double slope = 0.0;
     GF2_TRY(density_pass(c, d, p, F_in, static_cast<const double2 *>(Sigma_iw), Sigma1, &mu, P_out,
                          static_cast<double2 *>(G_iw_out), c->it_mom.as<double>(), &trPS, &e2b,
-                         &evals));
+                         &evals, &slope));
     *mu_inout = mu;
     double e1b = 0.0;
     if (F_out) {
@@ -333,11 +375,12 @@ extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, g
     r = c->it_tmp.as<double>() + 1024 + ne;
     int n_inner = 0, n_eval = 0;
     double e2b = 0.0, trPS = 0.0;
+    double slope = 0.0;   // dN/dmu carried from one mu search to the next
     bool converged = false;
     for (int it = 1; it <= p->max_inner; ++it) {
         int ev = 0;
         GF2_TRY(density_pass(c, d, p, F, Sig, Sig1, &mu, Pout, c->it_G_iw.as<double2>(),
-                             c->it_mom.as<double>(), &trPS, &e2b, &ev));
+                             c->it_mom.as<double>(), &trPS, &e2b, &ev, &slope));
         n_eval += ev;
         n_inner = it;
         if (!have_Pin) {

@@ -42,12 +42,40 @@ struct DysonArgs {
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// 1/x to full FP64 precision: hardware reciprocal estimate + two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// 1/a for complex a, scaled so that |a|^2 cannot overflow or underflow
 __device__ __forceinline__ double2 cinv(double2 a) {
-    // 1/a with scaling to avoid overflow of |a|^2
     const double s = fmax(fabs(a.x), fabs(a.y));
-    const double ar = a.x / s, ai = a.y / s;
-    const double d = s * (ar * ar + ai * ai);
-    return make_double2(ar / d, -ai / d);
+    const double is = rcp_nr(s);
+    const double ar = a.x * is, ai = a.y * is;
+    const double id = rcp_nr(ar * ar + ai * ai) * is;
+    return make_double2(ar * id, -ai * id);
+}
+
+// Rotate a value by k lanes within each row of 16 lanes (DPP row_ror:k).
+template <int K> __device__ __forceinline__ int ror16(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xF, 0xF, false);
+}
+template <int K> __device__ __forceinline__ double ror16(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = ror16<K>((int)(b & 0xffffffffLL));
+    const int hi = ror16<K>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int K> __device__ __forceinline__ void argmax_step(double &best, int &bi) {
+    const double ob = ror16<K>(best);
+    const int oi = ror16<K>(bi);
+    const bool take = ob > best || (ob == best && oi < bi);
+    best = take ? ob : best;
+    bi = take ? oi : bi;
 }
 
 template <int RA, int CB, int TC>
@@ -138,15 +166,11 @@ __global__ __launch_bounds__(DY_TR * TC) void k_dyson(DysonArgs a) {
                         }
                     }
                 }
-                // argmax over the 16 owners (consecutive lanes); ties -> smaller row
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) {
-                    const double ob = __shfl_xor(best, off, 16);
-                    const int oi = __shfl_xor(bi, off, 16);
-                    const bool take = ob > best || (ob == best && oi < bi);
-                    best = take ? ob : best;
-                    bi = take ? oi : bi;
-                }
+                // argmax over the 16 owners (one DPP row of 16 lanes); ties -> smaller row
+                argmax_step<8>(best, bi);
+                argmax_step<4>(best, bi);
+                argmax_step<2>(best, bi);
+                argmax_step<1>(best, bi);
                 if (tr == 0) sh_r[buf] = (best > 0.0 && bi < n) ? bi : -1;
             }
             __syncthreads();

@@ -205,7 +205,7 @@ def test_fock_matches_oracle(torch, n):
 # ---------------------------------------------------------------------------
 # one pass of 2.a-2.b
 
-@pytest.mark.parametrize("method", ["bisect", "illinois"])
+@pytest.mark.parametrize("method", ["bisect", "illinois", "secant"])
 def test_density_fock_matches_oracle(torch, method):
     from paper_1405_3273_amd import make_params
     s = generic_system(10, 0, naux=30, beta=50.0, niw=2048, ntau=257)

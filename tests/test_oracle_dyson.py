@@ -37,10 +37,16 @@ def test_density_and_mu_match_fermi_dirac_closed_form():
     s = _sys()
     eps, C = R.generalized_eig(s.h, s.S)
     mu_ref = R.mu_closed_form(eps, s.nelec, s.beta)
-    for method in ("bisect", "illinois"):
+    for method in ("bisect", "illinois", "secant"):
         mu, _ = O.find_mu(s.nelec, s.S, s.h, None, None, s.beta, s.niw, mu0=0.0,
                           method=method, tol_N=1e-12)
         assert mu == pytest.approx(mu_ref, abs=1e-7)
+    # a good slope hint and a nearby start need very few evaluations
+    mu1, ev1, sl = O.find_mu(s.nelec, s.S, s.h, None, None, s.beta, s.niw, mu0=mu_ref + 0.01,
+                             method="secant", tol_N=1e-12, return_slope=True)
+    mu2, ev2, _ = O.find_mu(s.nelec, s.S, s.h, None, None, s.beta, s.niw, mu0=mu_ref + 1e-4,
+                            method="secant", tol_N=1e-12, slope=sl, return_slope=True)
+    assert sl > 0 and mu2 == pytest.approx(mu_ref, abs=1e-7) and ev2 <= 4
     G = O.green_iw(mu_ref, s.S, s.h, None, s.beta, s.niw)
     P = O.density_from_giw(G, *O.tail_moments(s.S, s.h, mu_ref), s.beta)
     assert np.max(np.abs(P - R.hf_density(s.S, s.h, mu_ref, s.beta))) < 1e-9
