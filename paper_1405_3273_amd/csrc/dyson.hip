@@ -79,7 +79,7 @@ template <int K> __device__ __forceinline__ void argmax_step(double &best, int &
 }
 
 template <int RA, int CB, int TC>
-__global__ __launch_bounds__(DY_TR * TC) void k_dyson(DysonArgs a) {
+__global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
     const int n = a.n;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -368,7 +368,8 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
     const int RA = (n + DY_TR - 1) / DY_TR;
     const bool full = mode != GF2_DYSON_TRACE;
-    const bool p_in_lds = full && ne * 8 <= 96 * 1024;
+    // a large LDS accumulator would keep a second workgroup off the CU
+    const bool p_in_lds = full && ne * 8 <= 32 * 1024;
     const size_t shm = p_in_lds ? ne * 8 : 0;
     int dev_cus = 256;
     (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
