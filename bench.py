@@ -137,6 +137,7 @@ def main():
 
     # dominant kernel class over the timed region
     kind = {"sigma_gemm": ("mfma", args.prec), "sigma_splitk": ("mfma", args.prec),
+            "sigma_s23": ("mfma", args.prec),
             "dyson": ("alu", "fp64_vector"), "t2i_expand": ("hbm", "hbm"),
             "i2t_fold": ("hbm", "hbm"), "fock": ("hbm", "hbm")}
     dom = max(prof, key=lambda k: prof[k][0])

@@ -225,8 +225,10 @@ int gf2_iterate(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
  * With profiling on, the context brackets every launch of the listed kernel
  * classes with a pair of HIP events on its stream and records the
  * algorithmic work of that launch:
- *   GF2_KC_SIGMA_GEMM    index transforms 1-3 of Eq. (Sigma); work = flops
+ *   GF2_KC_SIGMA_GEMM    first index transform of Eq. (Sigma) (contracts m); work = flops
  *   GF2_KC_SIGMA_SPLITK  final contraction of Eq. (Sigma);    work = flops
+ *   GF2_KC_SIGMA_S23     second and third index transforms, fused (contract q, k);
+ *                        work = flops (4 n^5 per tau point)
  *   GF2_KC_DYSON         Eq. (GF) inversions (any mode);       work = flops (8 n^3 per frequency)
  *   GF2_KC_T2I_EXPAND    Sigma(i w) expansion;                 work = bytes written (16 n^2 niw)
  *   GF2_KC_I2T_FOLD      G(i w) fold;                          work = bytes read (16 n^2 niw)
@@ -242,7 +244,8 @@ int gf2_iterate(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
 #define GF2_KC_T2I_EXPAND   3
 #define GF2_KC_I2T_FOLD     4
 #define GF2_KC_FOCK         5
-#define GF2_KC_COUNT        6
+#define GF2_KC_SIGMA_S23    6
+#define GF2_KC_COUNT        7
 
 int gf2_profile_enable(gf2_ctx *ctx, int on);
 int gf2_profile_read(gf2_ctx *ctx, int nslots, double *ms, long long *launches, double *work);

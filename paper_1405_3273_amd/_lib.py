@@ -48,8 +48,10 @@ GF2_KC_DYSON = 2
 GF2_KC_T2I_EXPAND = 3
 GF2_KC_I2T_FOLD = 4
 GF2_KC_FOCK = 5
-GF2_KC_COUNT = 6
-KERNEL_CLASSES = ("sigma_gemm", "sigma_splitk", "dyson", "t2i_expand", "i2t_fold", "fock")
+GF2_KC_SIGMA_S23 = 6
+GF2_KC_COUNT = 7
+KERNEL_CLASSES = ("sigma_gemm", "sigma_splitk", "dyson", "t2i_expand", "i2t_fold", "fock",
+                  "sigma_s23")
 
 
 class Gf2Error(RuntimeError):

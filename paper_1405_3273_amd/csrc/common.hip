@@ -320,8 +320,8 @@ int gf2_ctx_destroy(gf2_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     prof_release(c);
-    gf2::DevBuf *bufs[] = {&c->S,        &c->Sinv,      &c->h,       &c->v,        &c->V1_64,
-                           &c->W2_64,    &c->V1_32,     &c->W2_32,   &c->sig_T1,   &c->sig_T2,
+    gf2::DevBuf *bufs[] = {&c->S,        &c->Sinv,      &c->h,       &c->v,        &c->v_32,
+                           &c->W2_64,    &c->W2_32,     &c->W2_b3,   &c->sig_T1,   &c->sig_X,    &c->sig_Gp,  &c->sig_Gq,
                            &c->sig_G,    &c->sig_Gb,    &c->sig_part, &c->four_c,  &c->four_C,
                            &c->four_fold, &c->four_twid, &c->dys_part, &c->dys_X,   &c->dys_aux,
                            &c->dys_out,  &c->fock_part, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
@@ -340,6 +340,7 @@ int gf2_set_system(gf2_ctx *c, int n, const double *S, const double *h, const do
     const size_t n2 = (size_t)n * n, n4 = n2 * n2;
     c->has_system = false;
     c->have_f32_layouts = false;
+    c->have_bf3_layouts = false;
     c->n = n;
     GF2_TRY(c->S.ensure(n2 * 8));
     GF2_TRY(c->Sinv.ensure(n2 * 8));

@@ -69,13 +69,15 @@ struct gf2_ctx {
     std::vector<double> S_host, Sinv_host, h_host;
 
     // Layouts for the Sigma contraction, built once per system:
-    //   V1[m][q][k][i] = v_imqk     (first index transform contracts m)
-    //   W2[n][p][l][j] = 2 v_lpnj - v_nplj
-    gf2::DevBuf V1_64, W2_64, V1_32, W2_32;
+    //   v_32           FP32 copy of v (first index transform, FP32 and BF16x3)
+    //   W2[n][p][l][j] = 2 v_lpnj - v_nplj   (final contraction; FP64 and FP32)
+    //   W2_b3          W2 as bf16 hi/lo planes in the final contraction's K order
+    gf2::DevBuf v_32, W2_64, W2_32, W2_b3;
     bool have_f32_layouts = false;
+    bool have_bf3_layouts = false;
 
     // ---- workspaces (grow-only) ----
-    gf2::DevBuf sig_T1, sig_T2, sig_G, sig_Gb, sig_part;
+    gf2::DevBuf sig_T1, sig_X, sig_G, sig_Gb, sig_Gp, sig_Gq, sig_part;
     gf2::DevBuf four_c, four_C, four_fold, four_twid;
     gf2::DevBuf dys_part, dys_X, dys_aux, dys_out;
     gf2::DevBuf fock_part;

@@ -1,26 +1,24 @@
 // Eq. (Sigma): the second-order self-energy in imaginary time on MFMA.
 //
-// For every tau point (A = G(tau), B = G(-tau) = -G(beta - tau)) the six-index
-// sum is evaluated as four index transforms, each a GEMM with one large
-// dimension (cost 2 N^5 each, 8 N^5 per tau):
+// For every tau point (G = G(tau), Gb = G(-tau) = -G(beta - tau)) the
+// six-index sum is evaluated as four index transforms of 2 N^5 flops each:
 //
-//   S1  T1[q][k][i][n] = sum_m V1[m][q][k][i] A[m][n]       V1[m][q][k][i] = v_imqk
-//   S2  T2[k][i][n][p] = sum_q T1[q][k][i][n] B[q][p]
-//   S3  X [i][n][p][l] = sum_k T2[k][i][n][p] A[k][l]
-//   S4  Sigma[i][j]    = - sum_{n,p,l} X[i][n][p][l] W2[n][p][l][j]
-//                                                           W2[n][p][l][j] = 2 v_lpnj - v_nplj
+//   S1   T1[i][n][q][k] = sum_m G[m][n] v_imqk                (GEMM batched over i)
+//   S23  X[i][n][p][l]  = sum_{q,k} Gb[q][p] T1[i][n][q][k] G[k][l]
+//                         (two products per N x N slab, fused in one kernel)
+//   S4   Sigma[i][j]    = - sum_{n,p,l} X[i][n][p][l] W2[n][p][l][j]
+//                         W2[n][p][l][j] = 2 v_lpnj - v_nplj   (split-K GEMM, K = N^3)
 //
-// S1-S3 have the form C[r][c] = sum_a T[a][r] M[a][c] with r running over
-// N^3 rows; S4 is a split-K GEMM with K = N^3 whose partial sums are added
-// in FP64 in a fixed order.  Several tau points run in one launch (grid z,
-// and stacked rows in S4).  G is symmetric, so A and B are used as stored.
+// A batch of b tau points runs per pass: S1 stacks the b G matrices along
+// its rows, S23 and S4 index the batch in their grids/rows.  G is symmetric,
+// so G and Gb are used as stored.  The split-K partial sums of S4 are added
+// in FP64 in a fixed order, so results do not depend on scheduling.
 //
 // Arithmetic: FP64 MFMA (v_mfma_f64_16x16x4f64), FP32 MFMA
 // (v_mfma_f32_16x16x4f32), or BF16x3: each FP32 operand x is split into
-// hi = bf16(x), lo = bf16(x - hi) when it is staged into LDS, and
-// a*b ~ hi_a*lo_b + lo_a*hi_b + hi_a*hi_b on v_mfma_f32_16x16x32_bf16 with
-// FP32 accumulation.  In S4 the FP32 accumulators are flushed into FP64
-// registers every 512 K elements.
+// hi = bf16(x), lo = bf16(x - hi) and a*b ~ hi_a*lo_b + lo_a*hi_b + hi_a*hi_b
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  In S4 the FP32
+// accumulators are flushed into FP64 registers every 512 K.
 #include "gf2_internal.h"
 
 #include <algorithm>
@@ -50,38 +48,41 @@ struct GemmArgs {
     int split;           // z indexes K slices (1) or independent batches (0)
     double alpha;
     int vecA;            // 1 if 4-element vector loads of A are aligned
+    // bf16 hi/lo plane output (gemm_bf3<.., PLANES = true>): column n = q*pn + k
+    // goes to C[z*sC + m*ldc + q*pld + k] (hi) and the same index + plane (lo)
+    int pn, pld;
+    long long plane;
 };
 
 constexpr int NTHREADS = 256;
 constexpr int BM = 128;  // 4 waves x 2 row tiles x 16
 constexpr int RT = 2;    // row tiles per wave
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-    unsigned int u = __float_as_uint(x);
-    unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(r >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(unsigned short h) {
-    return __uint_as_float(((unsigned int)h) << 16);
-}
+// x = hi + lo + O(2^-16 |x|): hi = bf16(x), lo = bf16(x - hi), round to nearest even
+// (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ void split_bf16(float x, unsigned short &hi, unsigned short &lo) {
-    hi = bf16_rne(x);
-    lo = bf16_rne(x - bf16_to_f(hi));
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    hi = __builtin_bit_cast(unsigned short, h);
+    lo = __builtin_bit_cast(unsigned short, l);
 }
 
 template <class T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 
 // ---------------------------------------------------------------------------
 // FP64 / FP32 kernel: LDS tiles As[k][m], Bs[k][n]
-template <int MODE, bool AK, int NT>
+// OUT64: FP64 output (FP32 accumulators flushed into FP64 every 512 K);
+// BK_: K chunk (0 = the mode's default; the k-major form needs 16).
+template <int MODE, bool AK, int NT, bool OUT64, int BK_>
 __global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
     using in_t = typename ModeT<MODE>::in_t;
     using acc_t = typename ModeT<MODE>::acc_t;
-    constexpr int BK = ModeT<MODE>::BK;
+    constexpr int BK = BK_ ? BK_ : ModeT<MODE>::BK;
+    static_assert(!AK || BK == 16, "k-major A loads assume 16-element chunks");
+    static_assert(BK % 4 == 0 && (BK * BM) % NTHREADS == 0, "bad chunk");
     constexpr int BN = 16 * NT;
     constexpr int SA = BM + 16;                       // padded row strides
     constexpr int SB = BN + ((16 - BN % 32) + 32) % 32;
-    constexpr bool OUT64 = !AK || MODE == MODE_F64;   // S4 writes FP64 partials
     constexpr int FLUSH = 512 / BK;                   // chunks between FP64 flushes
 
     __shared__ in_t As[BK][SA];
@@ -247,13 +248,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
 
 // ---------------------------------------------------------------------------
 // BF16x3 kernel: FP32 operands split into hi/lo BF16 in LDS, tiles As[m][k], Bs[n][k]
-template <bool AK, int NT>
+// PLANES: output split into bf16 hi/lo planes (see GemmArgs), else FP32.
+template <bool AK, int NT, bool PLANES>
 __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
     constexpr int BK = 32;
     constexpr int BN = 16 * NT;
     constexpr int SK = BK + 8;       // padded k stride (bf16 elements)
-    constexpr bool OUT64 = !AK;
-    constexpr int FLUSH = 512 / BK;
 
     __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][SK];
     __shared__ __attribute__((aligned(16))) unsigned short Al[BM][SK];
@@ -273,15 +273,10 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
     if (Kz <= 0) return;
 
     v4f acc[RT][NT];
-    double accd[RT][NT][4];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            acc[r][c] = v4f{0, 0, 0, 0};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) accd[r][c][e] = 0.0;
-        }
+        for (int c = 0; c < NT; ++c) acc[r][c] = v4f{0, 0, 0, 0};
 
     // A staging: each thread owns one row m and 16 consecutive k (BM*BK/256 = 16)
     const int a_m = AK ? (tid % BM) : (tid / 2);
@@ -386,50 +381,50 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
                 acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][c], 0, 0, 0);
             }
         }
-        if constexpr (OUT64) {
-            if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
-#pragma unroll
-                for (int r = 0; r < RT; ++r)
-#pragma unroll
-                    for (int c = 0; c < NT; ++c) {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) accd[r][c][e] += (double)acc[r][c][e];
-                        acc[r][c] = v4f{0, 0, 0, 0};
-                    }
-            }
-        }
     }
 
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+    for (int c = 0; c < NT; ++c) {
+        const int n = nb + c * 16 + (lane & 15);
+        int pq = 0, pk = 0;
+        if constexpr (PLANES) {
+            pq = n / g.pn;
+            pk = n - pq * g.pn;
+        }
 #pragma unroll
-        for (int c = 0; c < NT; ++c)
+        for (int r = 0; r < RT; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const long long m = mb + wave * (16 * RT) + r * 16 + 4 * (lane >> 4) + e;
-                const int n = nb + c * 16 + (lane & 15);
                 if (m < g.M && n < g.N) {
-                    if constexpr (OUT64)
-                        static_cast<double *>(g.C)[(long long)z * g.sC + m * g.ldc + n] =
-                            g.alpha * accd[r][c][e];
-                    else
-                        static_cast<float *>(g.C)[(long long)z * g.sC + m * g.ldc + n] =
-                            (float)(g.alpha * (double)acc[r][c][e]);
+                    const float x = (float)(g.alpha * (double)acc[r][c][e]);
+                    if constexpr (PLANES) {
+                        unsigned short hi, lo;
+                        split_bf16(x, hi, lo);
+                        unsigned short *C = static_cast<unsigned short *>(g.C);
+                        const long long idx = (long long)z * g.sC + m * g.ldc + (long long)pq * g.pld + pk;
+                        C[idx] = hi;
+                        C[idx + g.plane] = lo;
+                    } else {
+                        static_cast<float *>(g.C)[(long long)z * g.sC + m * g.ldc + n] = x;
+                    }
                 }
             }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // host-side dispatch
 
-template <int MODE, bool AK>
+// OUT64: FP64 output for gemm_fp; for gemm_bf3 it selects the hi/lo plane output.
+template <int MODE, bool AK, bool OUT64, int BK_>
 static void launch_nt(int nt, dim3 grid, hipStream_t s, const GemmArgs &g) {
-#define GF2_NT_CASE(T)                                                              \
-    case T:                                                                         \
-        if constexpr (MODE == MODE_BF3)                                             \
-            hipLaunchKernelGGL((gemm_bf3<AK, T>), grid, dim3(NTHREADS), 0, s, g);  \
-        else                                                                        \
-            hipLaunchKernelGGL((gemm_fp<MODE, AK, T>), grid, dim3(NTHREADS), 0, s, g); \
+#define GF2_NT_CASE(T)                                                                      \
+    case T:                                                                                 \
+        if constexpr (MODE == MODE_BF3)                                                     \
+            hipLaunchKernelGGL((gemm_bf3<AK, T, OUT64>), grid, dim3(NTHREADS), 0, s, g);    \
+        else                                                                                \
+            hipLaunchKernelGGL((gemm_fp<MODE, AK, T, OUT64, BK_>), grid, dim3(NTHREADS), 0, s, g); \
         break;
     switch (nt) {
         GF2_NT_CASE(1) GF2_NT_CASE(2) GF2_NT_CASE(3) GF2_NT_CASE(4)
@@ -446,22 +441,10 @@ static void col_blocking(int N, int &nt, int &nblocks) {
     nt = (tiles + nblocks - 1) / nblocks;
 }
 
-static int gemm(gf2_ctx *c, int mode, bool ak, GemmArgs g, int zcount) {
-    int nt, nblk;
+static dim3 gemm_grid(const GemmArgs &g, int zcount, int &nt) {
+    int nblk;
     col_blocking(g.N, nt, nblk);
-    dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)nblk, (unsigned)zcount);
-    if (mode == MODE_F64) {
-        if (ak) launch_nt<MODE_F64, true>(nt, grid, c->stream, g);
-        else launch_nt<MODE_F64, false>(nt, grid, c->stream, g);
-    } else if (mode == MODE_F32) {
-        if (ak) launch_nt<MODE_F32, true>(nt, grid, c->stream, g);
-        else launch_nt<MODE_F32, false>(nt, grid, c->stream, g);
-    } else {
-        if (ak) launch_nt<MODE_BF3, true>(nt, grid, c->stream, g);
-        else launch_nt<MODE_BF3, false>(nt, grid, c->stream, g);
-    }
-    GF2_HIP(hipGetLastError());
-    return GF2_OK;
+    return dim3((unsigned)((g.M + BM - 1) / BM), (unsigned)nblk, (unsigned)zcount);
 }
 
 int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a) {
@@ -472,40 +455,72 @@ int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a) {
     g.M = a.M; g.N = a.N; g.K = a.K; g.kz = a.K; g.split = 0;
     g.alpha = a.alpha;
     g.vecA = (a.lda % 2 == 0) ? 1 : 0;
-    return gemm(c, MODE_F64, true, g, 1);
+    int nt;
+    const dim3 grid = gemm_grid(g, 1, nt);
+    launch_nt<MODE_F64, true, true, 0>(nt, grid, c->stream, g);
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block order.  Consecutive workgroup ids are handed to the 8 XCDs
+// in turn; the remap gives every XCD a contiguous range of logical blocks, so
+// blocks that share operands (neighbouring logical ids) share one L2.  The
+// grid is launched with 8 * ceil(total / 8) blocks; ids past `total` exit.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_logical(int total) {
+    const int per = (total + NXCD - 1) / NXCD;
+    return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+}
+static unsigned xcd_grid(long long total) {
+    return (unsigned)(((total + NXCD - 1) / NXCD) * NXCD);
+}
+
+// k / n for k < 2^22 (K = n^3 <= 160^3): the float quotient is within 1/8 of
+// k / n, so its truncation is off by at most one and one correction fixes it.
+__device__ __forceinline__ unsigned udiv22(unsigned k, unsigned n, float inv_n) {
+    unsigned q = (unsigned)((float)k * inv_n);
+    const int r = (int)k - (int)(q * n);
+    if (r < 0) --q;
+    else if (r >= (int)n) ++q;
+    return q;
 }
 
 // ---------------------------------------------------------------------------
 // layouts of v (built once per system)
 
+// W2[n][p][l][j] = 2 v_lpnj - v_nplj (idx = ((n*N + p)*N + l)*N + j)
 template <class T>
-__global__ void k_build_layouts(int n, const double *__restrict__ v, T *__restrict__ V1,
-                                T *__restrict__ W2) {
+__global__ void k_build_w2(int n, const double *__restrict__ v, T *__restrict__ W2) {
     const size_t n2 = (size_t)n * n, n3 = n2 * n, n4 = n3 * n;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n4;
          idx += (size_t)gridDim.x * blockDim.x) {
-        // idx = ((a*n + b)*n + c)*n + d
         const size_t a = idx / n3, b = (idx / n2) % n, cc = (idx / n) % n, d = idx % n;
-        // V1[m=a][q=b][k=cc][i=d] = v[i][m][q][k]
-        V1[idx] = (T)v[((d * n + a) * n + b) * n + cc];
-        // W2[n=a][p=b][l=cc][j=d] = 2 v[l][p][n][j] - v[n][p][l][j]
         W2[idx] = (T)(2.0 * v[((cc * n + b) * n + a) * n + d] - v[((a * n + b) * n + cc) * n + d]);
     }
+}
+
+__global__ void k_to_f32(size_t count, const double *__restrict__ x, float *__restrict__ y) {
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < count;
+         idx += (size_t)gridDim.x * blockDim.x)
+        y[idx] = (float)x[idx];
 }
 
 int sigma_build_layouts(gf2_ctx *c, bool want_f32) {
     const size_t n = c->n, n4 = n * n * n * n;
     const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 65536);
-    GF2_TRY(c->V1_64.ensure(n4 * 8));
     GF2_TRY(c->W2_64.ensure(n4 * 8));
-    hipLaunchKernelGGL(k_build_layouts<double>, dim3(blocks), dim3(256), 0, c->stream, (int)n,
-                       c->v.as<double>(), c->V1_64.as<double>(), c->W2_64.as<double>());
+    hipLaunchKernelGGL(k_build_w2<double>, dim3(blocks), dim3(256), 0, c->stream, (int)n,
+                       c->v.as<double>(), c->W2_64.as<double>());
     GF2_HIP(hipGetLastError());
     if (want_f32) {
-        GF2_TRY(c->V1_32.ensure(n4 * 4));
+        GF2_TRY(c->v_32.ensure(n4 * 4));
         GF2_TRY(c->W2_32.ensure(n4 * 4));
-        hipLaunchKernelGGL(k_build_layouts<float>, dim3(blocks), dim3(256), 0, c->stream, (int)n,
-                           c->v.as<double>(), c->V1_32.as<float>(), c->W2_32.as<float>());
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, c->stream, n4,
+                           c->v.as<double>(), c->v_32.as<float>());
+        GF2_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_build_w2<float>, dim3(blocks), dim3(256), 0, c->stream, (int)n,
+                           c->v.as<double>(), c->W2_32.as<float>());
         GF2_HIP(hipGetLastError());
         c->have_f32_layouts = true;
     }
@@ -513,9 +528,9 @@ int sigma_build_layouts(gf2_ctx *c, bool want_f32) {
 }
 
 // ---------------------------------------------------------------------------
-// per-batch staging and reduction
-
-// Gs[t] = G(tau_{k0+t}), Gbs[t] = G(-tau_{k0+t}) = -G(tau_{M-k0-t})
+// per-batch staging
+//
+// Gs[t] = G(tau_{k0+t}), Gbs[t] = G(-tau_{k0+t}) = -G(tau_{M-k0-t})   ([nb][n][n])
 template <class T>
 __global__ void k_stage_g(int n, int M, int k0, int nb, const double *__restrict__ Gt,
                           T *__restrict__ Gs, T *__restrict__ Gbs) {
@@ -530,117 +545,1130 @@ __global__ void k_stage_g(int n, int M, int k0, int nb, const double *__restrict
     }
 }
 
+// Operand copy of G(tau) for the third transform: Gp[t][l][col], l < 16*KT,
+// col < SL, zero outside l, k < n.  Column col holds k = col, except in the
+// FP64 form, where within each 16-block col = 4a + b holds k = a + 4b (the
+// order in which an FP64 MFMA result tile hands out its rows).
+template <class T, bool PERM>
+__global__ void k_stage_gp(int n, int kt_tiles, int sl, int M, int k0, int nb,
+                           const double *__restrict__ Gt, T *__restrict__ Gp) {
+    const int p16 = 16 * kt_tiles;
+    const size_t per = (size_t)p16 * sl;
+    const size_t n2 = (size_t)n * n;
+    const size_t total = per * nb;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t t = idx / per;
+        const int rem = (int)(idx % per);
+        const int l = rem / sl, col = rem % sl;
+        int k = col;
+        if (PERM) k = (col & ~15) + ((col & 15) >> 2) + 4 * (col & 3);
+        double val = 0.0;
+        if (col < p16 && l < n && k < n) val = Gt[(size_t)(k0 + t) * n2 + (size_t)l * n + k];
+        Gp[idx] = (T)val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused second and third transforms.
+//
+// For one tau point t and one (i, n) pair the first transform left the
+// N x N slab T1[q][k] (= sum_m v_imqk G_mn).  Per slab
+//     X[p][l] = sum_{q,k} Gb[q][p] T1[q][k] G[k][l],
+// computed as Y^T = T1^T Gb (contract q) and X^T = G^T Y^T (contract k).
+// A wave owns one 16-wide p tile of one slab: Y^T[:, p tile] stays in MFMA
+// accumulators and is fed back unchanged as the B operand of the second
+// product.  That works because an MFMA result tile holds, per lane, the rows
+// of one K group of the next product's B operand (rows 4a..4a+3 for FP32,
+// a, a+4, a+8, a+12 for FP64, a = lane/16); the A operand (G) is read in the
+// matching row order.  Workgroup = (t, n, p tile); its waves take the slabs
+// i = w, w + nw, ...; G(tau) sits in LDS (or is read from the staged copy
+// when it does not fit), the p-tile columns of G(-tau) too.
+//
+// Layouts: T1[i][t][n][q][k] (one contiguous slab per (i, t, n));
+//          X[n][p][r][l] with r = t*N + i (the final contraction reads,
+//          for each (n, p), a contiguous block of rows).
+struct S23Args {
+    const void *T1;
+    const void *Gp;   // [nb][16*KT][SL]
+    const void *Gb;   // [nb][n][n]
+    void *X;
+    int n, nb;
+};
+
+template <int MODE> struct S23Geom {
+    static constexpr int pad = (MODE == MODE_F64) ? 2 : 4;   // conflict-free 16-B row reads
+};
+
+#ifndef S23_DB
+#define S23_DB 1      // double-buffered operand groups in the first product
+#endif
+
+// Workgroup size bound: the grouped FP32 form keeps 100-200 registers live
+// (at most 8 waves); the FP64 form fits in 128 registers up to 7 tiles and
+// then runs 16 waves per workgroup, which is what one workgroup per CU
+// (G(tau) in LDS takes ~100 KB) needs to fill the SIMDs.
+template <int MODE, int KT> struct S23Threads {
+    static constexpr int value = (MODE == MODE_F64 && KT <= 7) ? 1024 : 512;
+};
+
+template <int MODE, int KT, bool GLDS>
+__global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(S23Args a) {
+    using T = typename ModeT<MODE>::in_t;
+    using acc_t = typename ModeT<MODE>::acc_t;
+    constexpr int P16 = 16 * KT;
+    constexpr int SL = P16 + S23Geom<MODE>::pad;
+    extern __shared__ __attribute__((aligned(16))) unsigned char s23_smem[];
+
+    const int N = a.n;
+    const int total = a.nb * N * KT;
+    const int L = xcd_logical(total);
+    if (L >= total) return;
+    const int pt = L % KT;
+    const int nn = (L / KT) % N;
+    const int t = L / (KT * N);
+    const int S = (N + 3) >> 2;                    // q steps of 4
+
+    T *Gl = reinterpret_cast<T *>(s23_smem);
+    T *Bl = Gl + (GLDS ? P16 * SL : 0);            // [4S][16]: G(-tau)[q][16 pt + c]
+    const T *Gsrc = static_cast<const T *>(a.Gp) + (size_t)t * P16 * SL;
+    const T *Gb = static_cast<const T *>(a.Gb) + (size_t)t * N * N;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if constexpr (GLDS) {
+        const int n16 = P16 * SL * (int)sizeof(T) / 16;
+        const float4 *src = reinterpret_cast<const float4 *>(Gsrc);
+        float4 *dst = reinterpret_cast<float4 *>(Gl);
+        for (int e = tid; e < n16; e += nth) dst[e] = src[e];
+    }
+    // q order of the first product: with GW = 16 B / element (4 FP32, 2 FP64)
+    // and N % GW == 0 the first U = N / (4 GW) groups of 4 GW q are taken as
+    // step GW u + j <-> q = 4 GW u + GW a + j (a = lane/16), so that a lane
+    // reads GW consecutive q of one slab row with one 16-B load; the
+    // remaining q (and every q when N % GW != 0) as step s <-> q = 4s + a.
+    // Bl[step][a][c] = G(-tau)[q(step, a)][16 pt + c].
+    constexpr int GW = 16 / (int)sizeof(T);      // q per 16-B load: 4 (FP32), 2 (FP64)
+    // (FP64 keeps one q per load: its grouped form needs too many registers)
+    const bool vq = (MODE != MODE_F64) && (N % GW == 0);
+    const int U = vq ? N / (4 * GW) : 0;
+    for (int e = tid; e < 4 * S * 16; e += nth) {
+        const int st = e >> 6, ga = (e >> 4) & 3, p = 16 * pt + (e & 15);
+        const int q = (st < GW * U) ? 4 * GW * (st / GW) + GW * ga + (st % GW) : 4 * st + ga;
+        Bl[e] = (q < N && p < N) ? Gb[(size_t)q * N + p] : T(0);
+    }
+    __syncthreads();
+
+    const T *Gop = GLDS ? Gl : Gsrc;
+    const int lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int nw = nth >> 6;
+    const size_t N2 = (size_t)N * N;
+    const size_t R = (size_t)a.nb * N;
+    const T *T1 = static_cast<const T *>(a.T1);
+    T *X = static_cast<T *>(a.X);
+    const int p = 16 * pt + c;
+    const bool vec4 = (MODE != MODE_F64) && (N % 4 == 0);
+
+    // Operand loads use clamped addresses instead of masks: a row q >= N meets
+    // a zero row of Gb, a column k >= N gives a row of Y^T that meets a zero
+    // row of G in the second product, so the (finite) values read there add
+    // exact zeros.  This keeps the loads free of value selects, which would
+    // force a wait right after they are issued.
+    //
+    // The slab is symmetric (v_imqk = v_imkq), so T1[q][k] is read as
+    // T1[k][q]: in the grouped q order a lane's 4 consecutive q of row k are
+    // one 16-B load.
+    const int kc_last = min(16 * (KT - 1) + c, N - 1);
+    auto slab_of = [&](int i) { return T1 + (((size_t)i * a.nb + t) * N + nn) * N2; };
+    typedef T qv_t __attribute__((ext_vector_type(GW)));
+    qv_t ga_[KT];                               // grouped operands (GW steps each)
+#if S23_DB
+    qv_t gb_[KT];
+#endif
+    T ta[KT];                                   // one step of the remaining q
+    auto loadg = [&](qv_t(&r)[KT], const T *slab, int u) {
+        const T *col = slab + 4 * GW * u + GW * g;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
+            r[kt] = *reinterpret_cast<const qv_t *>(col + (size_t)k * N);
+        }
+    };
+    auto load1 = [&](T(&r)[KT], const T *slab, int st) {
+        const T *row = slab + (size_t)min(4 * st + g, N - 1) * N;
+#pragma unroll
+        for (int kt = 0; kt < KT - 1; ++kt) r[kt] = row[16 * kt + c];
+        r[KT - 1] = row[kc_last];
+    };
+
+    int i = tid >> 6;
+    if (i < N) {
+        if (U > 0) loadg(ga_, slab_of(i), 0);
+        else load1(ta, slab_of(i), 0);
+    }
+    for (; i < N; i += nw) {
+        const T *slab = slab_of(i);
+        acc_t acc1[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) acc1[kt] = acc_t{0, 0, 0, 0};
+
+        // ---- Y^T[k][p] = sum_q T1[q][k] Gb[q][p]
+        auto mma = [&](T av, T bv, int kt) {
+            if constexpr (MODE == MODE_F64)
+                acc1[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1[kt], 0, 0, 0);
+            else
+                acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc1[kt], 0, 0, 0);
+        };
+        auto stepg = [&](const qv_t(&r)[KT], int u) {
+#pragma unroll
+            for (int j = 0; j < GW; ++j) {
+                const T bv = Bl[(GW * u + j) * 64 + lane];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) mma(r[kt][j], bv, kt);
+            }
+        };
+        auto step1 = [&](const T(&r)[KT], int st) {
+            const T bv = Bl[st * 64 + lane];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) mma(r[kt], bv, kt);
+        };
+        if (U > 0) {
+            // the first ungrouped step is loaded now; it is used last
+            if (GW * U < S) load1(ta, slab, GW * U);
+#if S23_DB
+            int u = 0;
+            for (; u + 1 < U; u += 2) {
+                loadg(gb_, slab, u + 1);
+                stepg(ga_, u);
+                if (u + 2 < U) loadg(ga_, slab, u + 2);
+                stepg(gb_, u + 1);
+            }
+            if (u < U) stepg(ga_, u);
+#else
+            for (int u = 0; u < U; ++u) {
+                stepg(ga_, u);
+                if (u + 1 < U) loadg(ga_, slab, u + 1);
+            }
+#endif
+        }
+        // remaining steps: the first was loaded ahead, later ones (N % 16 >= 8
+        // or N % 4 != 0) are loaded just before use
+        for (int st = GW * U; st < S; ++st) {
+            if (st > GW * U) load1(ta, slab, st);
+            step1(ta, st);
+        }
+        // first operands of the next slab, in flight during the second product
+        if (i + nw < N) {
+            if (U > 0) loadg(ga_, slab_of(i + nw), 0);
+            else load1(ta, slab_of(i + nw), 0);
+        }
+
+        // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p], one 16-row l tile at a time
+        T *xbase = X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+#pragma unroll 1
+        for (int lt = 0; lt < KT; ++lt) {
+            acc_t acc2 = acc_t{0, 0, 0, 0};
+            const T *grow = Gop + (16 * lt + c) * SL + 4 * g;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                if constexpr (MODE == MODE_F64) {
+                    const double2 g0 = *reinterpret_cast<const double2 *>(grow + 16 * kt);
+                    const double2 g1 = *reinterpret_cast<const double2 *>(grow + 16 * kt + 2);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.x, acc1[kt][0], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], acc2, 0, 0, 0);
+                } else {
+                    const float4 gv = *reinterpret_cast<const float4 *>(grow + 16 * kt);
+                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, acc1[kt][0], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], acc2, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], acc2, 0, 0, 0);
+                }
+            }
+            if (p < N) {
+                if constexpr (MODE == MODE_F64) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int l = 16 * lt + g + 4 * e;
+                        if (l < N) xbase[l] = acc2[e];
+                    }
+                } else {
+                    const int l0 = 16 * lt + 4 * g;
+                    if (vec4 && l0 < N) {
+                        *reinterpret_cast<float4 *>(xbase + l0) =
+                            make_float4(acc2[0], acc2[1], acc2[2], acc2[3]);
+                    } else if (!vec4) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (l0 + e < N) xbase[l0 + e] = acc2[e];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Final contraction: part[z][r][j] = - sum_{k in slice z} X(k, r) W2[k][j],
+// k = (n, p, l) flattened, X(k, r) = X[k / N][r][k % N] (layout above), so
+// for each (n, p) a block's rows are one contiguous piece of memory.
+// Split-K over slices of kz; FP32 accumulators are flushed into FP64 every
+// 512 K.  Workgroup = (row block, slice), XCD-ordered so that the row
+// blocks of one slice (which share the W2 slice) run on one XCD.
+struct S4Args {
+    const void *X;
+    const void *W;
+    double *part;
+    long long K, kz;
+    int n, R, nrb, nsplit;
+    int vec;            // n divisible by the vector width
+};
+
+constexpr int S4_WAVES = 8;               // one 16-row tile per wave
+constexpr int S4_THREADS = 64 * S4_WAVES;
+constexpr int S4_BM = 16 * S4_WAVES;
+
+template <int MODE, int NT>
+__global__ __launch_bounds__(S4_THREADS) void k_s4(S4Args a) {
+    using T = typename ModeT<MODE>::in_t;
+    using acc_t = typename ModeT<MODE>::acc_t;
+    constexpr bool F64 = (MODE == MODE_F64);
+    constexpr int VEC = 16 / (int)sizeof(T);          // elements per 16-B load
+    constexpr int BK = 8 * VEC;                       // 32 (FP32) / 16 (FP64)
+    constexpr int BMR = S4_BM;                        // rows per block
+    constexpr int BN = 16 * NT;
+    constexpr int SK = BK + (F64 ? 2 : 4);
+    constexpr int SB = BN + ((16 - BN % 32) + 32) % 32;
+    constexpr int A_IT = BMR * 8 / S4_THREADS;        // 16-B A loads per thread
+    constexpr int B_IT = (BK * BN / VEC + S4_THREADS - 1) / S4_THREADS;
+    constexpr int AROWS = S4_THREADS / 8;             // rows covered per A load round
+    constexpr int FLUSH = 512 / BK;
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+
+    __shared__ __attribute__((aligned(16))) T As[BMR][SK];
+    __shared__ __attribute__((aligned(16))) T Bs[BK][SB];
+
+    const int total = a.nrb * a.nsplit;
+    const int L = xcd_logical(total);
+    if (L >= total) return;
+    const int rb = L % a.nrb, z = L / a.nrb;
+    const int N = a.n;
+    const long long k0 = (long long)z * a.kz;
+    const long long kend = std::min<long long>(a.K, k0 + a.kz);
+    const int r0 = rb * BMR;
+    const T *X = static_cast<const T *>(a.X);
+    const T *W = static_cast<const T *>(a.W);
+    const size_t RN = (size_t)a.R * N;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kq = tid & 7, arow = tid >> 3;
+
+    acc_t acc[NT];
+    double accd[NT][4];
+#pragma unroll
+    for (int cc = 0; cc < NT; ++cc) {
+        acc[cc] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) accd[cc][e] = 0.0;
+    }
+
+    const float inv_n = 1.0f / (float)N;
+    vec_t ra[A_IT], rbv[B_IT];
+    auto load_chunk = [&](long long kb) {
+        const long long k = kb + VEC * kq;
+        const unsigned np = udiv22((unsigned)k, (unsigned)N, inv_n);
+        const int l = (int)(k - (long long)np * N);
+#pragma unroll
+        for (int j = 0; j < A_IT; ++j) {
+            const int r = r0 + arow + AROWS * j;
+            vec_t v;
+            if (a.vec) {
+                if (k < kend && r < a.R) {
+                    v = *reinterpret_cast<const vec_t *>(X + (size_t)np * RN + (size_t)r * N + l);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[e] = T(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const long long ke = k + e;
+                    T x = T(0);
+                    if (ke < kend && r < a.R) {
+                        const unsigned npe = udiv22((unsigned)ke, (unsigned)N, inv_n);
+                        const int le = (int)(ke - (long long)npe * N);
+                        x = X[(size_t)npe * RN + (size_t)r * N + le];
+                    }
+                    v[e] = x;
+                }
+            }
+            ra[j] = v;
+        }
+        // B chunk: rows kb .. kb + BK - 1 of W2, contiguous BK * N elements
+        const T *wb = W + (size_t)kb * N;
+        const long long nvalid = (std::min<long long>(kend, kb + BK) - kb) * N;
+#pragma unroll
+        for (int j = 0; j < B_IT; ++j) {
+            const int u = tid + j * S4_THREADS;
+            const long long e0 = (long long)u * VEC;
+            vec_t v;
+            if (a.vec) {
+                if (e0 < nvalid) v = *reinterpret_cast<const vec_t *>(wb + e0);
+                else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[e] = T(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = (e0 + e < nvalid) ? wb[e0 + e] : T(0);
+            }
+            rbv[j] = v;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int j = 0; j < A_IT; ++j)
+            *reinterpret_cast<vec_t *>(&As[arow + AROWS * j][VEC * kq]) = ra[j];
+#pragma unroll
+        for (int j = 0; j < B_IT; ++j) {
+            const int u = tid + j * S4_THREADS;
+            const int e0 = u * VEC;
+            if (e0 < BK * N) {
+                const int kr = e0 / N, col = e0 - kr * N;
+                if (a.vec) {
+                    *reinterpret_cast<vec_t *>(&Bs[kr][col]) = rbv[j];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int kk = (e0 + e) / N, cl = (e0 + e) - kk * N;
+                        if (kk < BK) Bs[kk][cl] = rbv[j][e];
+                    }
+                }
+            }
+        }
+    };
+
+    const int nchunks = (int)((kend - k0 + BK - 1) / BK);
+    load_chunk(k0);
+    for (int ch = 0; ch < nchunks; ++ch) {
+        __syncthreads();
+        store_chunk();
+        __syncthreads();
+        if (ch + 1 < nchunks) load_chunk(k0 + (long long)(ch + 1) * BK);
+#pragma unroll
+        for (int s4 = 0; s4 < BK; s4 += 4) {
+            const int kr = s4 + (lane >> 4);
+            const T af = As[wave * 16 + (lane & 15)][kr];
+#pragma unroll
+            for (int cc = 0; cc < NT; ++cc) {
+                const T bf = Bs[kr][cc * 16 + (lane & 15)];
+                if constexpr (F64)
+                    acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[cc], 0, 0, 0);
+                else
+                    acc[cc] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[cc], 0, 0, 0);
+            }
+        }
+        if constexpr (!F64) {
+            if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
+                    acc[cc] = acc_t{0, 0, 0, 0};
+                }
+            }
+        }
+    }
+
+    double *out = a.part + (size_t)z * RN;
+#pragma unroll
+    for (int cc = 0; cc < NT; ++cc)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = F64 ? ((lane >> 4) + 4 * e) : (4 * (lane >> 4) + e);
+            const int m = r0 + wave * 16 + row;
+            const int j = cc * 16 + (lane & 15);
+            if (m < a.R && j < N) {
+                double val;
+                if constexpr (F64) val = acc[cc][e];
+                else val = accd[cc][e];
+                out[(size_t)m * N + j] = -val;
+            }
+        }
+}
+
 // Sigma[k0 + t][i][j] = sum_z part[z][t*n + i][j]   (part already carries the minus sign)
 __global__ void k_reduce_split(int n, int nb, int nsplit, const double *__restrict__ part,
                                double *__restrict__ Sig, int k0) {
     const size_t n2 = (size_t)n * n;
     const size_t total = n2 * nb;
-    const size_t zs = total;  // partial stride: (nb*n) x n
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int z = 0; z < nsplit; ++z) s += part[z * zs + idx];
+        for (int z = 0; z < nsplit; ++z) s += part[z * total + idx];
         Sig[(size_t)k0 * n2 + idx] = s;
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 forms of S23 and S4.
+//
+// Operands are pre-split into bf16 hi and lo planes where they are produced
+// or staged, so the kernels issue loads and MFMAs only:
+//   T1  hi/lo planes [i][t][n][q][k] with rows padded to LQ = roundup(n, 8)
+//       (written by the first transform; padding is zero);
+//   Gq  hi/lo planes of G(tau) [t][l][col] for the third transform, col in
+//       the K order of a 32-deep MFMA fed by two FP32 result tiles (below);
+//   W2b hi/lo planes of W2 [k / 64][j][64] with k in the K order of the A
+//       operand of the final contraction (below), built once per system.
+// v_mfma_f32_16x16x32_bf16: lane (a = lane/16, c = lane%16) holds A[c][8a..8a+7]
+// and B[8a..8a+7][c]; the result tile is laid out like the FP32 MFMA's.
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8bf_t as_bf8(v8us x) { return __builtin_bit_cast(v8bf_t, x); }
+
+__device__ __forceinline__ void split8(const float (&x)[8], v8us &hi, v8us &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        unsigned short h, l;
+        split_bf16(x[e], h, l);
+        hi[e] = h;
+        lo[e] = l;
+    }
+}
+
+__device__ __forceinline__ v4f mma3(v8us ah, v8us al, v8us bh, v8us bl, v4f acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bl), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al), as_bf8(bh), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bh), acc, 0, 0, 0);
+    return acc;
+}
+
+// K order of a 32-deep product whose B operand is two FP32 16x16 result
+// tiles (rows 0-15 of tile 0, rows 0-15 of tile 1): slot 8a + j holds row
+// 4a + j of tile 0 for j < 4 and row 4a + j - 4 of tile 1 for j >= 4.
+__device__ __forceinline__ int pair_row(int slot) {
+    const int a = slot >> 3, j = slot & 7;
+    return (j < 4) ? 4 * a + j : 16 + 4 * a + (j - 4);
+}
+
+// Gq[t][l][col], col < 32 * KP: G(tau_{k0+t})[l][k], k = 32 (col / 32) + pair_row(col % 32)
+__global__ void k_stage_gq(int n, int KP, int sl, int p16, int k0, int nb, size_t plane,
+                           const double *__restrict__ Gt, unsigned short *__restrict__ Gq) {
+    const size_t per = (size_t)p16 * sl;
+    const size_t n2 = (size_t)n * n;
+    const size_t total = per * nb;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t t = idx / per;
+        const int rem = (int)(idx % per);
+        const int l = rem / sl, col = rem % sl;
+        const int k = 32 * (col >> 5) + pair_row(col & 31);
+        float x = 0.0f;
+        if (col < 32 * KP && l < n && k < n) x = (float)Gt[(size_t)(k0 + t) * n2 + (size_t)l * n + k];
+        unsigned short h, lo;
+        split_bf16(x, h, lo);
+        Gq[idx] = h;
+        Gq[idx + plane] = lo;
+    }
+}
+
+struct S23b3Args {
+    const unsigned short *T1;   // hi plane; lo plane at + t1_plane
+    long long t1_plane;
+    int lq;                     // padded slab row
+    const unsigned short *Gq;   // hi plane; lo plane at + gq_plane
+    long long gq_plane;
+    const float *Gb;            // G(-tau) [nb][n][n] FP32
+    float *X;                   // [n][n][R][n] FP32
+    int n, nb;
+};
+
+template <int KT>
+__global__ __launch_bounds__(512) void k_s23_bf3(S23b3Args a) {
+    constexpr int KP = (KT + 1) / 2;          // 32-deep k steps of the second product
+    constexpr int P16 = 16 * KT;
+    constexpr int SLG = 32 * KP + 8;          // LDS row of Gq (bf16)
+    extern __shared__ __attribute__((aligned(16))) unsigned char s23b_smem[];
+
+    const int N = a.n;
+    const int total = a.nb * N * KT;
+    const int L = xcd_logical(total);
+    if (L >= total) return;
+    const int pt = L % KT;
+    const int nn = (L / KT) % N;
+    const int t = L / (KT * N);
+    const int S32 = (N + 31) >> 5;            // 32-deep q steps of the first product
+    const int SQ = 32 * S32 + 8;              // LDS row of the G(-tau) slice (bf16)
+
+    unsigned short *GH = reinterpret_cast<unsigned short *>(s23b_smem);
+    unsigned short *GL = GH + P16 * SLG;
+    unsigned short *BH = GL + P16 * SLG;      // [16][SQ]: G(-tau)[q][16 pt + c] at [c][q]
+    unsigned short *BL = BH + 16 * SQ;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    {
+        const size_t off = (size_t)t * P16 * SLG;
+        const int n16 = P16 * SLG / 8;
+        const float4 *sh = reinterpret_cast<const float4 *>(a.Gq + off);
+        const float4 *sl = reinterpret_cast<const float4 *>(a.Gq + a.gq_plane + off);
+        float4 *dh = reinterpret_cast<float4 *>(GH);
+        float4 *dl = reinterpret_cast<float4 *>(GL);
+        for (int e = tid; e < n16; e += nth) {
+            dh[e] = sh[e];
+            dl[e] = sl[e];
+        }
+        const float *Gb = a.Gb + (size_t)t * N * N;
+        for (int e = tid; e < 16 * SQ; e += nth) {
+            const int cc = e / SQ, q = e - cc * SQ, p = 16 * pt + cc;
+            const float x = (q < N && p < N) ? Gb[(size_t)q * N + p] : 0.0f;
+            unsigned short h, l;
+            split_bf16(x, h, l);
+            BH[e] = h;
+            BL[e] = l;
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int nw = nth >> 6;
+    const size_t slab_sz = (size_t)N * a.lq;
+    const size_t R = (size_t)a.nb * N;
+    const int p = 16 * pt + c;
+    const bool vec4 = (N % 4 == 0);
+    // rows k >= N read row N - 1 (finite; they meet zero rows of G); q
+    // blocks past the padded row read q = 0 (they meet zero rows of G(-tau))
+    const int kc_last = min(16 * (KT - 1) + c, N - 1);
+    const unsigned short *T1h = a.T1;
+    const unsigned short *T1l = a.T1 + a.t1_plane;
+
+    for (int i = tid >> 6; i < N; i += nw) {
+        const size_t soff = (((size_t)i * a.nb + t) * N + nn) * slab_sz;
+        v4f acc1[2 * KP];
+#pragma unroll
+        for (int kt = 0; kt < 2 * KP; ++kt) acc1[kt] = v4f{0, 0, 0, 0};
+
+        // ---- Y^T[k][p] = sum_q T1[k][q] Gb[q][p]  (slab symmetric)
+        v8us ah[KT], al[KT];
+        auto load = [&](int s) {
+            int q0 = 32 * s + 8 * g;
+            if (q0 + 8 > a.lq) q0 = 0;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
+                const size_t o = soff + (size_t)k * a.lq + q0;
+                ah[kt] = *reinterpret_cast<const v8us *>(T1h + o);
+                al[kt] = *reinterpret_cast<const v8us *>(T1l + o);
+            }
+        };
+        load(0);
+        for (int s = 0; s < S32; ++s) {
+            const v8us bh = *reinterpret_cast<const v8us *>(BH + c * SQ + 32 * s + 8 * g);
+            const v8us bl = *reinterpret_cast<const v8us *>(BL + c * SQ + 32 * s + 8 * g);
+            v8us ch[KT], cl[KT];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                ch[kt] = ah[kt];
+                cl[kt] = al[kt];
+            }
+            if (s + 1 < S32) load(s + 1);
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) acc1[kt] = mma3(ch[kt], cl[kt], bh, bl, acc1[kt]);
+        }
+
+        // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p]; B operand = two result tiles
+        v8us yh[KP], yl[KP];
+#pragma unroll
+        for (int u = 0; u < KP; ++u) {
+            float y[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                y[e] = acc1[2 * u][e];
+                y[4 + e] = acc1[2 * u + 1][e];
+            }
+            split8(y, yh[u], yl[u]);
+        }
+        float *xbase = a.X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+#pragma unroll 1
+        for (int lt = 0; lt < KT; ++lt) {
+            v4f acc2 = v4f{0, 0, 0, 0};
+            const int row = (16 * lt + c) * SLG + 8 * g;
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                const v8us gh = *reinterpret_cast<const v8us *>(GH + row + 32 * u);
+                const v8us gl = *reinterpret_cast<const v8us *>(GL + row + 32 * u);
+                acc2 = mma3(gh, gl, yh[u], yl[u], acc2);
+            }
+            if (p < N) {
+                const int l0 = 16 * lt + 4 * g;
+                if (vec4 && l0 < N) {
+                    *reinterpret_cast<float4 *>(xbase + l0) = make_float4(acc2[0], acc2[1], acc2[2], acc2[3]);
+                } else if (!vec4) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (l0 + e < N) xbase[l0 + e] = acc2[e];
+                }
+            }
+        }
+    }
+}
+
+// W2b[kc][j][w] (hi; lo at + plane), w < 64: W2[k][j] with
+// k = 64 kc + 32 (w / 32) + pair_row(w % 32); zero for k >= n^3 or j >= n.
+__global__ void k_build_w2b(int n, int bn, long long nkc, size_t plane, const double *__restrict__ v,
+                            unsigned short *__restrict__ W2b) {
+    const size_t n2 = (size_t)n * n, n3 = n2 * n;
+    const size_t total = (size_t)nkc * bn * 64;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t kc = idx / ((size_t)bn * 64);
+        const int rem = (int)(idx % ((size_t)bn * 64));
+        const int j = rem >> 6, w = rem & 63;
+        const size_t k = 64 * kc + 32 * (w >> 5) + pair_row(w & 31);
+        float x = 0.0f;
+        if (k < n3 && j < n) {
+            // k = (nn, p, l): W2[nn][p][l][j] = 2 v_l p nn j - v_nn p l j
+            const size_t nn = k / n2, pp = (k / n) % n, l = k % n;
+            x = (float)(2.0 * v[((l * n + pp) * n + nn) * n + j] - v[((nn * n + pp) * n + l) * n + j]);
+        }
+        unsigned short h, lo;
+        split_bf16(x, h, lo);
+        W2b[idx] = h;
+        W2b[idx + plane] = lo;
+    }
+}
+
+// Final contraction in BF16x3.  Each wave owns 16 rows and reads its A
+// operand (X, FP32) straight from memory, splitting it in registers; the W2b
+// chunk (shared by the 8 waves) goes through LDS.  K order within a 32-deep
+// step: slot 8a + j <-> k = pair_row(8a + j), i.e. two runs of 4 consecutive k.
+struct S4b3Args {
+    const float *X;
+    const unsigned short *W2b;   // hi; lo at + plane
+    long long plane;
+    double *part;
+    long long K, kz;
+    int n, R, nrb, nsplit, vec;
+};
+
+template <int NT>
+__global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(S4b3Args a) {
+    constexpr int BK = 64;
+    constexpr int BN = 16 * NT;
+    constexpr int SKB = BK + 8;                       // LDS row (bf16)
+    constexpr int FLUSH = 512 / BK;
+    constexpr int B16 = BN * BK / 8;                  // 16-B units per plane per chunk
+    constexpr int B_IT = (B16 + S4_THREADS - 1) / S4_THREADS;
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][SKB];
+    __shared__ __attribute__((aligned(16))) unsigned short Bl[BN][SKB];
+
+    const int total = a.nrb * a.nsplit;
+    const int L = xcd_logical(total);
+    if (L >= total) return;
+    const int rb = L % a.nrb, z = L / a.nrb;
+    const int N = a.n;
+    const long long k0 = (long long)z * a.kz;
+    const long long kend = std::min<long long>(a.K, k0 + a.kz);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const size_t RN = (size_t)a.R * N;
+    const int r = std::min(rb * S4_BM + wave * 16 + c, a.R - 1);
+
+    v4f acc[NT];
+    double accd[NT][4];
+#pragma unroll
+    for (int cc = 0; cc < NT; ++cc) {
+        acc[cc] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) accd[cc][e] = 0.0;
+    }
+
+    // A: per 32-deep step two runs of 4 k (k = kb + 32 h + 4g .. and + 16)
+    const float inv_n = 1.0f / (float)N;
+    v4f ra[4];
+    auto load_a = [&](long long kb) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            long long k = kb + 32 * (h >> 1) + 16 * (h & 1) + 4 * g;
+            if (k >= a.K) k = 0;                          // meets zero rows of W2b
+            if (a.vec) {
+                const unsigned np = udiv22((unsigned)k, (unsigned)N, inv_n);
+                const int l = (int)(k - (long long)np * N);
+                ra[h] = *reinterpret_cast<const v4f *>(a.X + (size_t)np * RN + (size_t)r * N + l);
+            } else {
+                float x[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    long long ke = k + e;
+                    if (ke >= a.K) ke = 0;
+                    const unsigned np = udiv22((unsigned)ke, (unsigned)N, inv_n);
+                    const int l = (int)(ke - (long long)np * N);
+                    x[e] = a.X[(size_t)np * RN + (size_t)r * N + l];
+                }
+                ra[h] = v4f{x[0], x[1], x[2], x[3]};
+            }
+        }
+    };
+    v8us rbh[B_IT], rbl[B_IT];
+    auto load_b = [&](long long kb) {
+        const size_t base = (size_t)(kb / BK) * BN * BK;
+#pragma unroll
+        for (int j = 0; j < B_IT; ++j) {
+            // threads past the chunk reload its last unit (not stored): no
+            // conditional writes, which would put the staging arrays in scratch
+            const int u = min(tid + j * S4_THREADS, B16 - 1);
+            rbh[j] = *reinterpret_cast<const v8us *>(a.W2b + base + (size_t)u * 8);
+            rbl[j] = *reinterpret_cast<const v8us *>(a.W2b + a.plane + base + (size_t)u * 8);
+        }
+    };
+    auto store_b = [&]() {
+#pragma unroll
+        for (int j = 0; j < B_IT; ++j) {
+            // (clamped threads rewrite the last unit with the value it already has)
+            const int u = min(tid + j * S4_THREADS, B16 - 1);
+            const int jn = u / (BK / 8), w8 = u % (BK / 8);
+            *reinterpret_cast<v8us *>(&Bh[jn][8 * w8]) = rbh[j];
+            *reinterpret_cast<v8us *>(&Bl[jn][8 * w8]) = rbl[j];
+        }
+    };
+
+    const int nchunks = (int)((kend - k0 + BK - 1) / BK);
+    load_a(k0);
+    load_b(k0);
+    for (int ch = 0; ch < nchunks; ++ch) {
+        __syncthreads();
+        store_b();
+        __syncthreads();
+        v4f cur[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) cur[h] = ra[h];
+        if (ch + 1 < nchunks) {
+            load_a(k0 + (long long)(ch + 1) * BK);
+            load_b(k0 + (long long)(ch + 1) * BK);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float x[8] = {cur[2 * s][0], cur[2 * s][1], cur[2 * s][2], cur[2 * s][3],
+                          cur[2 * s + 1][0], cur[2 * s + 1][1], cur[2 * s + 1][2], cur[2 * s + 1][3]};
+            v8us xh, xl;
+            split8(x, xh, xl);
+#pragma unroll
+            for (int cc = 0; cc < NT; ++cc) {
+                const v8us bh = *reinterpret_cast<const v8us *>(&Bh[16 * cc + c][32 * s + 8 * g]);
+                const v8us bl = *reinterpret_cast<const v8us *>(&Bl[16 * cc + c][32 * s + 8 * g]);
+                acc[cc] = mma3(xh, xl, bh, bl, acc[cc]);
+            }
+        }
+        if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
+#pragma unroll
+            for (int cc = 0; cc < NT; ++cc) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
+                acc[cc] = v4f{0, 0, 0, 0};
+            }
+        }
+    }
+
+    double *out = a.part + (size_t)z * RN;
+#pragma unroll
+    for (int cc = 0; cc < NT; ++cc)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = rb * S4_BM + wave * 16 + 4 * g + e;
+            const int j = cc * 16 + c;
+            if (m < a.R && j < N) out[(size_t)m * N + j] = -accd[cc][e];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+template <int MODE, int KT>
+static int launch_s23_kt(gf2_ctx *c, const S23Args &a) {
+    using T = typename ModeT<MODE>::in_t;
+    constexpr int P16 = 16 * KT;
+    constexpr int SL = P16 + S23Geom<MODE>::pad;
+    const int S = (a.n + 3) / 4;
+    const size_t g_bytes = (size_t)P16 * SL * sizeof(T);
+    const size_t b_bytes = (size_t)4 * S * 16 * sizeof(T);
+    const bool glds = g_bytes + b_bytes <= (size_t)120 * 1024;
+    const size_t lds = (glds ? g_bytes : 0) + b_bytes;
+    // waves per workgroup: aim at ~16 resident waves per CU
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
+    const int waves = std::min(S23Threads<MODE, KT>::value / 64, std::max(4, 16 / per_cu));
+    const dim3 grid(xcd_grid((long long)a.nb * a.n * KT));
+    if (glds) {
+        GF2_HIP(hipFuncSetAttribute((const void *)k_s23<MODE, KT, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((k_s23<MODE, KT, true>), grid, dim3(64 * waves), lds, c->stream, a);
+    } else {
+        GF2_HIP(hipFuncSetAttribute((const void *)k_s23<MODE, KT, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((k_s23<MODE, KT, false>), grid, dim3(64 * waves), lds, c->stream, a);
+    }
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+template <int MODE>
+static int launch_s23(gf2_ctx *c, int kt, const S23Args &a) {
+    switch (kt) {
+        case 1: return launch_s23_kt<MODE, 1>(c, a);
+        case 2: return launch_s23_kt<MODE, 2>(c, a);
+        case 3: return launch_s23_kt<MODE, 3>(c, a);
+        case 4: return launch_s23_kt<MODE, 4>(c, a);
+        case 5: return launch_s23_kt<MODE, 5>(c, a);
+        case 6: return launch_s23_kt<MODE, 6>(c, a);
+        case 7: return launch_s23_kt<MODE, 7>(c, a);
+        case 8: return launch_s23_kt<MODE, 8>(c, a);
+        case 9: return launch_s23_kt<MODE, 9>(c, a);
+        case 10: return launch_s23_kt<MODE, 10>(c, a);
+        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+    }
+}
+
+template <int MODE>
+static int launch_s4(gf2_ctx *c, int nt, const S4Args &a) {
+    const dim3 grid(xcd_grid((long long)a.nrb * a.nsplit));
+#define GF2_S4_CASE(T_)                                                                    \
+    case T_:                                                                               \
+        hipLaunchKernelGGL((k_s4<MODE, T_>), grid, dim3(S4_THREADS), 0, c->stream, a);     \
+        break;
+    switch (nt) {
+        GF2_S4_CASE(1) GF2_S4_CASE(2) GF2_S4_CASE(3) GF2_S4_CASE(4) GF2_S4_CASE(5)
+        GF2_S4_CASE(6) GF2_S4_CASE(7) GF2_S4_CASE(8) GF2_S4_CASE(9) GF2_S4_CASE(10)
+        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+    }
+#undef GF2_S4_CASE
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+template <int KT>
+static int launch_s23_bf3_kt(gf2_ctx *c, const S23b3Args &a) {
+    constexpr int KP = (KT + 1) / 2;
+    constexpr int P16 = 16 * KT;
+    constexpr int SLG = 32 * KP + 8;
+    const int SQ = 32 * ((a.n + 31) / 32) + 8;
+    const size_t lds = 2 * ((size_t)2 * P16 * SLG + (size_t)2 * 16 * SQ);
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
+    const int waves = std::min(8, std::max(4, 16 / per_cu));
+    const dim3 grid(xcd_grid((long long)a.nb * a.n * KT));
+    GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_s23_bf3<KT>), grid, dim3(64 * waves), lds, c->stream, a);
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+static int launch_s23_bf3(gf2_ctx *c, int kt, const S23b3Args &a) {
+    switch (kt) {
+        case 1: return launch_s23_bf3_kt<1>(c, a);
+        case 2: return launch_s23_bf3_kt<2>(c, a);
+        case 3: return launch_s23_bf3_kt<3>(c, a);
+        case 4: return launch_s23_bf3_kt<4>(c, a);
+        case 5: return launch_s23_bf3_kt<5>(c, a);
+        case 6: return launch_s23_bf3_kt<6>(c, a);
+        case 7: return launch_s23_bf3_kt<7>(c, a);
+        case 8: return launch_s23_bf3_kt<8>(c, a);
+        case 9: return launch_s23_bf3_kt<9>(c, a);
+        case 10: return launch_s23_bf3_kt<10>(c, a);
+        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+    }
+}
+
+static int launch_s4_bf3(gf2_ctx *c, int nt, const S4b3Args &a) {
+    const dim3 grid(xcd_grid((long long)a.nrb * a.nsplit));
+#define GF2_S4B_CASE(T_)                                                                    \
+    case T_:                                                                                \
+        hipLaunchKernelGGL((k_s4_bf3<T_>), grid, dim3(S4_THREADS), 0, c->stream, a);        \
+        break;
+    switch (nt) {
+        GF2_S4B_CASE(1) GF2_S4B_CASE(2) GF2_S4B_CASE(3) GF2_S4B_CASE(4) GF2_S4B_CASE(5)
+        GF2_S4B_CASE(6) GF2_S4B_CASE(7) GF2_S4B_CASE(8) GF2_S4B_CASE(9) GF2_S4B_CASE(10)
+        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+    }
+#undef GF2_S4B_CASE
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+// W2 planes for the BF16x3 final contraction (once per system)
+static int build_bf3_layouts(gf2_ctx *c) {
+    const long long n = c->n, n3 = n * n * n;
+    const int bn = 16 * (int)((n + 15) / 16);
+    const long long nkc = (n3 + 63) / 64;
+    const size_t plane = (size_t)nkc * bn * 64;
+    GF2_TRY(c->W2_b3.ensure(2 * plane * 2));
+    const unsigned blocks = (unsigned)std::min<size_t>((plane + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_build_w2b, dim3(blocks), dim3(256), 0, c->stream, (int)n, bn, nkc, plane,
+                       c->v.as<double>(), c->W2_b3.as<unsigned short>());
+    GF2_HIP(hipGetLastError());
+    c->have_bf3_layouts = true;
+    return GF2_OK;
+}
+
 int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau) {
     const int n = c->n;
+    if (n > 160) return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
     const int ntau = d->ntau;
     const int M = ntau - 1;
     const long long N = n, N2 = N * N, N3 = N2 * N, N4 = N3 * N;
     const int mode = prec;
+    if (mode == MODE_BF3 && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
     const size_t esz = (mode == MODE_F64) ? 8 : 4;
     if (mode != MODE_F64 && !c->have_f32_layouts) GF2_TRY(sigma_build_layouts(c, true));
-    const void *V1 = (mode == MODE_F64) ? c->V1_64.ptr : c->V1_32.ptr;
+    const void *V = (mode == MODE_F64) ? c->v.ptr : c->v_32.ptr;
     const void *W2 = (mode == MODE_F64) ? c->W2_64.ptr : c->W2_32.ptr;
+    const int KT = (n + 15) / 16;
+    const int SL = 16 * KT + ((mode == MODE_F64) ? S23Geom<MODE_F64>::pad : S23Geom<MODE_F32>::pad);
 
-    // tau batch: two intermediates of b*N^4 elements, capped at ~16 GB
+    // tau batch: T1 and X hold b * N^4 elements each, capped at ~16 GB together
     const size_t budget = (size_t)16 << 30;
     const size_t bmax = std::max<size_t>(1, budget / (2 * (size_t)N4 * esz));
     const int b = (int)std::min<size_t>(bmax, (size_t)std::min(ntau, 64));
 
-    // split-K for S4: K = N^3 split into slices of kz (multiple of 512)
+    // final contraction: K = N^3 split into slices of kz (a multiple of 512)
     long long kz = 4096;
     if (N3 < 8 * 4096) kz = std::max<long long>(512, ((N3 / 8) + 511) / 512 * 512);
     const int nsplit = (int)((N3 + kz - 1) / kz);
+    const int NT = KT;
 
+    // BF16x3: T1 as hi/lo planes with rows padded to lq (zeroed once per call:
+    // the first transform never writes the padding)
+    const int lq = (n + 7) / 8 * 8;
+    const int KP = (KT + 1) / 2;
+    const int SLG = 32 * KP + 8;
+    const size_t t1_plane = (size_t)b * N2 * N * lq;
+    const size_t gq_plane = (size_t)b * 16 * KT * SLG;
+    if (mode == MODE_BF3) {
+        GF2_TRY(c->sig_T1.ensure(2 * t1_plane * 2));
+        GF2_TRY(c->sig_Gq.ensure(2 * gq_plane * 2));
+        GF2_TRY(fill_zero(c, c->sig_T1.ptr, 2 * t1_plane * 2));
+    }
     GF2_TRY(c->sig_T1.ensure((size_t)b * N4 * esz));
-    GF2_TRY(c->sig_T2.ensure((size_t)b * N4 * esz));
+    GF2_TRY(c->sig_X.ensure((size_t)b * N4 * esz));
     GF2_TRY(c->sig_G.ensure((size_t)b * N2 * esz));
     GF2_TRY(c->sig_Gb.ensure((size_t)b * N2 * esz));
+    GF2_TRY(c->sig_Gp.ensure((size_t)b * 16 * KT * SL * esz));
     GF2_TRY(c->sig_part.ensure((size_t)nsplit * b * N2 * 8));
 
-    const bool vec = (N3 % 4 == 0);
     for (int k0 = 0; k0 < ntau; k0 += b) {
         const int nb = std::min(b, ntau - k0);
         {
             const size_t tot = (size_t)nb * N2;
             const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
-            if (mode == MODE_F64)
+            const size_t totp = (size_t)nb * 16 * KT * SL;
+            const unsigned blocksp = (unsigned)std::min<size_t>((totp + 255) / 256, 4096);
+            if (mode == MODE_F64) {
                 hipLaunchKernelGGL(k_stage_g<double>, dim3(blocks), dim3(256), 0, c->stream, n, M,
                                    k0, nb, G_tau, c->sig_G.as<double>(), c->sig_Gb.as<double>());
-            else
+                hipLaunchKernelGGL((k_stage_gp<double, true>), dim3(blocksp), dim3(256), 0,
+                                   c->stream, n, KT, SL, M, k0, nb, G_tau, c->sig_Gp.as<double>());
+            } else {
                 hipLaunchKernelGGL(k_stage_g<float>, dim3(blocks), dim3(256), 0, c->stream, n, M,
                                    k0, nb, G_tau, c->sig_G.as<float>(), c->sig_Gb.as<float>());
+                if (mode == MODE_F32) {
+                    hipLaunchKernelGGL((k_stage_gp<float, false>), dim3(blocksp), dim3(256), 0,
+                                       c->stream, n, KT, SL, M, k0, nb, G_tau, c->sig_Gp.as<float>());
+                } else {
+                    const size_t totq = (size_t)nb * 16 * KT * SLG;
+                    const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
+                    hipLaunchKernelGGL(k_stage_gq, dim3(blocksq), dim3(256), 0, c->stream, n, KP,
+                                       SLG, 16 * KT, k0, nb, gq_plane, G_tau,
+                                       c->sig_Gq.as<unsigned short>());
+                }
+            }
             GF2_HIP(hipGetLastError());
         }
-        GemmArgs g{};
-        g.M = (int)N3;
-        g.N = n;
-        g.K = n;
-        g.kz = n;
-        g.split = 0;
-        g.alpha = 1.0;
-        g.vecA = vec ? 1 : 0;
-        g.lda = N3;
-        g.ldb = N;
-        g.ldc = N;
-        g.sB = N2;
-        g.sC = N4;
-        const double stage_flops = 2.0 * (double)N4 * (double)N * nb;
-        // S1: T1 = V1^T A   (A = G(tau))
-        g.A = V1; g.sA = 0;
-        g.B = c->sig_G.ptr;
-        g.C = c->sig_T1.ptr;
-        int ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
-        GF2_TRY(gemm(c, mode, true, g, nb));
-        prof_end(c, ph, stage_flops);
-        // S2: T2 = T1 x_q B   (B = G(-tau))
-        g.A = c->sig_T1.ptr; g.sA = N4;
-        g.B = c->sig_Gb.ptr;
-        g.C = c->sig_T2.ptr;
-        ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
-        GF2_TRY(gemm(c, mode, true, g, nb));
-        prof_end(c, ph, stage_flops);
-        // S3: X = T2 x_k A  (into T1)
-        g.A = c->sig_T2.ptr; g.sA = N4;
-        g.B = c->sig_G.ptr;
-        g.C = c->sig_T1.ptr;
-        ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
-        GF2_TRY(gemm(c, mode, true, g, nb));
-        prof_end(c, ph, stage_flops);
-        // S4: partial[z] = -X[(t,i)][K-slice z] W2[K-slice z][j]
-        GemmArgs h{};
-        h.A = c->sig_T1.ptr;
-        h.lda = N3;
-        h.sA = kz;
-        h.B = W2;
-        h.ldb = N;
-        h.sB = kz * N;
-        h.C = c->sig_part.ptr;
-        h.ldc = N;
-        h.sC = (long long)nb * N2;
-        h.M = (int)(nb * N);
-        h.N = n;
-        h.K = (int)N3;
-        h.kz = (int)kz;
-        h.split = 1;
-        h.alpha = -1.0;
-        h.vecA = vec ? 1 : 0;
-        ph = prof_begin(c, GF2_KC_SIGMA_SPLITK);
-        GF2_TRY(gemm(c, mode, false, h, nsplit));
-        prof_end(c, ph, stage_flops);
+        const long long R = (long long)nb * N;
+
+        // S1: T1[i][(t,n)][(q,k)] = sum_m Gs[(t,n)][m] v[i][m][(q,k)], batched over i
+        {
+            GemmArgs g{};
+            g.A = c->sig_G.ptr; g.lda = N; g.sA = 0;
+            g.B = V; g.ldb = N2; g.sB = N3;
+            g.C = c->sig_T1.ptr; g.ldc = N2; g.sC = R * N2;
+            g.M = (int)R; g.N = (int)N2; g.K = n; g.kz = n; g.split = 0;
+            g.alpha = 1.0;
+            g.vecA = 0;
+            int nt;
+            const dim3 grid = gemm_grid(g, n, nt);
+            const int ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
+            if (mode == MODE_F64) {
+                launch_nt<MODE_F64, false, true, 16>(nt, grid, c->stream, g);
+            } else if (mode == MODE_BF3) {
+                g.vecA = (n % 4 == 0) ? 1 : 0;
+                g.pn = n;
+                g.pld = lq;
+                g.ldc = N * lq;
+                g.sC = R * N * lq;
+                g.plane = (long long)t1_plane;
+                launch_nt<MODE_BF3, false, true, 0>(nt, grid, c->stream, g);
+            } else if (n % 16 != 0 && n % 20 == 0) {
+                launch_nt<MODE_F32, false, false, 20>(nt, grid, c->stream, g);
+            } else {
+                launch_nt<MODE_F32, false, false, 16>(nt, grid, c->stream, g);
+            }
+            GF2_HIP(hipGetLastError());
+            prof_end(c, ph, 2.0 * (double)N4 * (double)N * nb);
+        }
+        // S2 + S3 fused
+        {
+            const int ph = prof_begin(c, GF2_KC_SIGMA_S23);
+            if (mode == MODE_BF3) {
+                S23b3Args a{};
+                a.T1 = c->sig_T1.as<unsigned short>();
+                a.t1_plane = (long long)t1_plane;
+                a.lq = lq;
+                a.Gq = c->sig_Gq.as<unsigned short>();
+                a.gq_plane = (long long)gq_plane;
+                a.Gb = c->sig_Gb.as<float>();
+                a.X = c->sig_X.as<float>();
+                a.n = n;
+                a.nb = nb;
+                GF2_TRY(launch_s23_bf3(c, KT, a));
+            } else {
+                S23Args a{c->sig_T1.ptr, c->sig_Gp.ptr, c->sig_Gb.ptr, c->sig_X.ptr, n, nb};
+                if (mode == MODE_F64) GF2_TRY(launch_s23<MODE_F64>(c, KT, a));
+                else GF2_TRY(launch_s23<MODE_F32>(c, KT, a));
+            }
+            prof_end(c, ph, 4.0 * (double)N4 * (double)N * nb);
+        }
+        // S4: split-K final contraction
+        {
+            S4Args a{};
+            a.X = c->sig_X.ptr;
+            a.W = W2;
+            a.part = c->sig_part.as<double>();
+            a.K = N3;
+            a.kz = kz;
+            a.n = n;
+            a.R = (int)R;
+            a.nrb = (int)((R + S4_BM - 1) / S4_BM);
+            a.nsplit = nsplit;
+            a.vec = (mode == MODE_F64) ? (n % 2 == 0) : (n % 4 == 0);
+            const int ph = prof_begin(c, GF2_KC_SIGMA_SPLITK);
+            if (mode == MODE_F64) {
+                GF2_TRY(launch_s4<MODE_F64>(c, NT, a));
+            } else if (mode == MODE_F32) {
+                GF2_TRY(launch_s4<MODE_F32>(c, NT, a));
+            } else {
+                const long long nkc = (N3 + 63) / 64;
+                S4b3Args ab{};
+                ab.X = c->sig_X.as<float>();
+                ab.W2b = c->W2_b3.as<unsigned short>();
+                ab.plane = nkc * 16 * NT * 64;
+                ab.part = a.part;
+                ab.K = a.K;
+                ab.kz = a.kz;
+                ab.n = n;
+                ab.R = a.R;
+                ab.nrb = a.nrb;
+                ab.nsplit = a.nsplit;
+                ab.vec = (n % 4 == 0);
+                GF2_TRY(launch_s4_bf3(c, NT, ab));
+            }
+            prof_end(c, ph, 2.0 * (double)N4 * (double)N * nb);
+        }
         {
             const size_t tot = (size_t)nb * N2;
             const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);

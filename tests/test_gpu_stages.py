@@ -35,7 +35,8 @@ def _relerr(got, ref):
 # ---------------------------------------------------------------------------
 # Eq. (Sigma)
 
-@pytest.mark.parametrize("n,ntau", [(1, 5), (3, 9), (10, 257), (17, 12), (33, 6), (40, 5)])
+@pytest.mark.parametrize("n,ntau", [(1, 5), (3, 9), (10, 257), (16, 7), (17, 12), (33, 6),
+                                    (40, 5), (48, 4)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_sigma_tau_matches_oracle(torch, n, ntau, prec):
     print(f"sigma n={n} ntau={ntau} prec={prec}", flush=True)
@@ -62,6 +63,23 @@ def test_sigma_tau_n100_sampled(torch, prec):
     ref = O.sigma_tau(Gt, s.v, taus=[0, 2, 5])
     g = _gf2(s)
     got = g.sigma_tau(_dev(torch, Gt), prec).cpu().numpy()[[0, 2, 5]]
+    err = _relerr(got, ref)
+    print(f"  rel err {err:.3e}")
+    assert err <= TOL_SIGMA[prec]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_sigma_tau_n120_sampled(torch, prec):
+    """N=120: eight 16-row tiles (the FP64 form reads G(tau) from memory, not LDS)."""
+    print(f"sigma n=120 prec={prec}", flush=True)
+    n, ntau = 120, 5
+    s = generic_system(n, 310, naux=360, half_band=12, diag=(-3.0, -0.3), beta=200.0, ntau=ntau)
+    rng = np.random.default_rng(8)
+    Gt = random_tau_stack(rng, ntau, n, scale=0.05)
+    ref = O.sigma_tau(Gt, s.v, taus=[1, 4])
+    g = _gf2(s)
+    got = g.sigma_tau(_dev(torch, Gt), prec).cpu().numpy()[[1, 4]]
     err = _relerr(got, ref)
     print(f"  rel err {err:.3e}")
     assert err <= TOL_SIGMA[prec]
