@@ -221,6 +221,27 @@ int gf2_density_fock(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
 int gf2_iterate(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
                 gf2_state *st, gf2_report *rep);
 
+/* gf2_iterate_batched: one outer iteration (as gf2_iterate) for each of nsys
+ * independent systems, e.g. a geometry sweep with uneven n -- the systems of
+ * the paper's sweeps are independent problems, so they share launches only.
+ * ctxs[s] (host array of nsys distinct contexts on one device) holds system
+ * s (gf2_set_system), dims[s] its sizes and states[s] its state (device
+ * arrays as for gf2_iterate); prm applies to all.  Everything runs on
+ * ctxs[0]'s stream (the other contexts' streams are synchronised first and
+ * left untouched).  The inner loops advance in lockstep: each round solves
+ * Eq. (GF) at the pending mu of every system's search, or its density pass,
+ * as one replay of a captured HIP graph (tail moments, the inversions of all
+ * systems grouped by size class, the reductions); every system gets the
+ * workgroups and arithmetic of gf2_iterate, so its result is the same.
+ * reports[s] as gf2_iterate, except that ms_sigma, ms_fourier, ms_inner and
+ * ms_total are the times of the whole batch.  Errors: as gf2_iterate for any
+ * system; GF2_EINVAL for nsys < 1, NULL arrays, a repeated context or
+ * contexts on different devices.  On error the states of all systems are
+ * unspecified.
+ */
+int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
+                        const gf2_params *prm, gf2_state *states, gf2_report *reports);
+
 /* ---- opt-in kernel timing -------------------------------------------------
  * With profiling on, the context brackets every launch of the listed kernel
  * classes with a pair of HIP events on its stream and records the

@@ -40,7 +40,7 @@ GF2_MU_SECANT = 2
 
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
-            "gf2_iterate", "gf2_profile_enable", "gf2_profile_read")
+            "gf2_iterate", "gf2_iterate_batched", "gf2_profile_enable", "gf2_profile_read")
 
 GF2_KC_SIGMA_GEMM = 0
 GF2_KC_SIGMA_SPLITK = 1
@@ -114,6 +114,8 @@ def load(path: str = None):
                               vp, vp, dp], i),
         "gf2_iterate": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), C.POINTER(gf2_state),
                          C.POINTER(gf2_report)], i),
+        "gf2_iterate_batched": ([C.POINTER(vp), i, C.POINTER(gf2_dims), C.POINTER(gf2_params),
+                                 C.POINTER(gf2_state), C.POINTER(gf2_report)], i),
         "gf2_profile_enable": ([vp, i], i),
         "gf2_profile_read": ([vp, i, dp, C.POINTER(C.c_longlong), dp], i),
     }
@@ -215,6 +217,22 @@ def gf2_iterate(ctx, dims: gf2_dims, params: gf2_params, state: gf2_state) -> gf
     rep = gf2_report()
     _check(load().gf2_iterate(ctx, C.byref(dims), C.byref(params), C.byref(state), C.byref(rep)))
     return rep
+
+
+def gf2_iterate_batched(ctxs, dims, params: gf2_params, states):
+    """ctxs, dims, states: sequences of equal length; states are updated in place."""
+    n = len(ctxs)
+    if not (len(dims) == len(states) == n):
+        raise ValueError("gf2_iterate_batched: ctxs, dims and states differ in length")
+    c_arr = (C.c_void_p * n)(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    d_arr = (gf2_dims * n)(*dims)
+    s_arr = (gf2_state * n)(*states)
+    r_arr = (gf2_report * n)()
+    code = load().gf2_iterate_batched(c_arr, n, d_arr, C.byref(params), s_arr, r_arr)
+    for k in range(n):   # copy the updated states back
+        C.memmove(C.addressof(states[k]), C.addressof(s_arr[k]), C.sizeof(gf2_state))
+    _check(code)
+    return [r_arr[k] for k in range(n)]
 
 
 def gf2_profile_enable(ctx, on: bool = True):

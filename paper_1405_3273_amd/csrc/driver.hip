@@ -40,103 +40,186 @@ static int particle_excess(gf2_ctx *c, const gf2_dims *d, double mu, const doubl
     return GF2_OK;
 }
 
-// Returns mu and the number of evaluations; *slope is read (hint, <= 0 = none)
-// and replaced by the secant slope dN/dmu of the final bracket when known.
-static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
-                   const double2 *Sig, double mu0, double *mu_out, int *evals_out,
-                   double *slope) {
-    const int n = c->n;
-    if (d->nelec < 0 || d->nelec > 2 * n)
-        return fail(GF2_EBRACKET, "mu search: nelec outside [0, 2n]");
+// The mu search as a resumable state machine: start() sets the first mu to
+// evaluate (pending); feed(N(pending) - nelec) either finishes (done, mu) or
+// sets the next pending mu.  One search per system; the batched driver runs
+// many of them in lockstep, one Dyson launch per round.
+struct MuSearch {
+    const gf2_params *p = nullptr;
+    double hint = 0.0;                // slope dN/dmu from the previous search (<= 0: none)
+    double slope = 0.0;               // slope of the final bracket (valid if have_slope)
+    bool have_slope = false;
     int evals = 0;
-    double lo, hi, f_lo, f_hi;
-    auto finish = [&](double mu, double l, double fl, double h, double fh, bool have) {
-        if (have && h > l && fh > fl && slope) *slope = (fh - fl) / (h - l);
-        *mu_out = mu;
-        *evals_out = evals;
-        return GF2_OK;
-    };
-    if (p->mu_method == GF2_MU_SECANT) {
-        double a = mu0, fa, fb;
-        GF2_TRY(particle_excess(c, d, a, F, Sig, &fa));
-        ++evals;
-        if (std::fabs(fa) < p->tol_N) return finish(a, 0, 0, 0, 0, false);
-        const double s_ = (slope && *slope > 0.0) ? *slope : 1.0 / p->mu_halfwidth;
-        double step = -fa / s_;
-        const double mag = std::fmin(std::fmax(std::fabs(step), 4.0 * p->tol_mu), p->mu_halfwidth);
-        step = step > 0.0 ? mag : -mag;
-        double b = a + step;
-        for (;;) {
-            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no bracket found");
-            GF2_TRY(particle_excess(c, d, b, F, Sig, &fb));
-            ++evals;
-            if (std::fabs(fb) < p->tol_N) {
-                if (a < b) return finish(b, a, fa, b, fb, true);
-                return finish(b, b, fb, a, fa, true);
-            }
-            if ((fb > 0.0) != (fa > 0.0)) break;
-            const double nb = b + 2.0 * (b - a);
-            a = b;
-            fa = fb;
-            b = nb;
-        }
-        if (a < b) { lo = a; f_lo = fa; hi = b; f_hi = fb; }
-        else       { lo = b; f_lo = fb; hi = a; f_hi = fa; }
-    } else {
-        lo = mu0 - p->mu_halfwidth;
-        hi = mu0 + p->mu_halfwidth;
-        GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
-        ++evals;
-        while (f_lo > 0.0) {
-            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no lower bracket end");
-            const double w = hi - lo;
-            hi = lo;
-            lo = lo - w;
-            GF2_TRY(particle_excess(c, d, lo, F, Sig, &f_lo));
-            ++evals;
-        }
-        GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
-        ++evals;
-        while (f_hi < 0.0) {
-            if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no upper bracket end");
-            const double w = hi - lo;
-            lo = hi;
-            hi = hi + w;
-            GF2_TRY(particle_excess(c, d, hi, F, Sig, &f_hi));
-            ++evals;
+    int stage = 0;                    // 1 secant start, 2 secant expansion, 3 lower end,
+                                      // 4 upper end, 5 interior
+    double a = 0, fa = 0, b = 0, fb = 0, lo = 0, hi = 0, f_lo = 0, f_hi = 0, t_lo = 0, t_hi = 0;
+    int side = 0, istep = 0;
+    double pending = 0.0;
+    bool done = false;
+    double mu = 0.0;
+
+    void start(const gf2_params *prm, double mu0, double slope_hint) {
+        p = prm;
+        hint = slope_hint;
+        have_slope = false;
+        evals = 0;
+        done = false;
+        side = 0;
+        istep = 0;
+        if (p->mu_method == GF2_MU_SECANT) {
+            a = mu0;
+            stage = 1;
+            pending = a;
+        } else {
+            lo = mu0 - p->mu_halfwidth;
+            hi = mu0 + p->mu_halfwidth;
+            stage = 3;
+            pending = lo;
         }
     }
-    double t_lo = f_lo, t_hi = f_hi;   // true values at the bracket ends
-    int side = 0;
-    for (int step = 0; step < p->max_bisect; ++step) {
+    void finish(double m, double l, double fl, double h, double fh, bool have) {
+        if (have && h > l && fh > fl) {
+            slope = (fh - fl) / (h - l);
+            have_slope = true;
+        }
+        mu = m;
+        done = true;
+    }
+    int next_interior() {
+        if (istep >= p->max_bisect) return fail(GF2_ENOCONV, "mu search did not converge");
         double mid = 0.5 * (lo + hi);
         if (p->mu_method != GF2_MU_BISECT && f_hi > f_lo) {
             const double x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
             if (lo < x && x < hi) mid = x;
         }
-        double fm;
-        GF2_TRY(particle_excess(c, d, mid, F, Sig, &fm));
-        ++evals;
-        if (std::fabs(fm) < p->tol_N) {
-            if (fm < 0.0) return finish(mid, mid, fm, hi, t_hi, true);
-            return finish(mid, lo, t_lo, mid, fm, true);
-        }
-        if (fm < 0.0) {
-            lo = mid;
-            f_lo = fm;
-            t_lo = fm;
-            if (side == -1) f_hi *= 0.5;
-            side = -1;
-        } else {
-            hi = mid;
-            f_hi = fm;
-            t_hi = fm;
-            if (side == 1) f_lo *= 0.5;
-            side = 1;
-        }
-        if (hi - lo < p->tol_mu) return finish(0.5 * (lo + hi), lo, t_lo, hi, t_hi, true);
+        pending = mid;
+        stage = 5;
+        return GF2_OK;
     }
-    return fail(GF2_ENOCONV, "mu search did not converge");
+    int enter_interior() {
+        t_lo = f_lo;
+        t_hi = f_hi;
+        side = 0;
+        istep = 0;
+        return next_interior();
+    }
+    int feed(double f) {
+        ++evals;
+        switch (stage) {
+            case 1: {
+                fa = f;
+                if (std::fabs(fa) < p->tol_N) {
+                    finish(a, 0, 0, 0, 0, false);
+                    return GF2_OK;
+                }
+                const double s_ = (hint > 0.0) ? hint : 1.0 / p->mu_halfwidth;
+                double step = -fa / s_;
+                const double mag =
+                    std::fmin(std::fmax(std::fabs(step), 4.0 * p->tol_mu), p->mu_halfwidth);
+                step = step > 0.0 ? mag : -mag;
+                b = a + step;
+                if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no bracket found");
+                stage = 2;
+                pending = b;
+                return GF2_OK;
+            }
+            case 2: {
+                fb = f;
+                if (std::fabs(fb) < p->tol_N) {
+                    if (a < b) finish(b, a, fa, b, fb, true);
+                    else finish(b, b, fb, a, fa, true);
+                    return GF2_OK;
+                }
+                if ((fb > 0.0) != (fa > 0.0)) {
+                    if (a < b) { lo = a; f_lo = fa; hi = b; f_hi = fb; }
+                    else       { lo = b; f_lo = fb; hi = a; f_hi = fa; }
+                    return enter_interior();
+                }
+                const double nb = b + 2.0 * (b - a);
+                a = b;
+                fa = fb;
+                b = nb;
+                if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no bracket found");
+                pending = b;
+                return GF2_OK;
+            }
+            case 3: {
+                f_lo = f;
+                if (f_lo > 0.0) {
+                    if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no lower bracket end");
+                    const double w = hi - lo;
+                    hi = lo;
+                    lo = lo - w;
+                    pending = lo;
+                    return GF2_OK;
+                }
+                stage = 4;
+                pending = hi;
+                return GF2_OK;
+            }
+            case 4: {
+                f_hi = f;
+                if (f_hi < 0.0) {
+                    if (evals > p->max_bisect) return fail(GF2_EBRACKET, "mu search: no upper bracket end");
+                    const double w = hi - lo;
+                    lo = hi;
+                    hi = hi + w;
+                    pending = hi;
+                    return GF2_OK;
+                }
+                return enter_interior();
+            }
+            case 5: {
+                const double mid = pending, fm = f;
+                if (std::fabs(fm) < p->tol_N) {
+                    if (fm < 0.0) finish(mid, mid, fm, hi, t_hi, true);
+                    else finish(mid, lo, t_lo, mid, fm, true);
+                    return GF2_OK;
+                }
+                if (fm < 0.0) {
+                    lo = mid;
+                    f_lo = fm;
+                    t_lo = fm;
+                    if (side == -1) f_hi *= 0.5;
+                    side = -1;
+                } else {
+                    hi = mid;
+                    f_hi = fm;
+                    t_hi = fm;
+                    if (side == 1) f_lo *= 0.5;
+                    side = 1;
+                }
+                if (hi - lo < p->tol_mu) {
+                    finish(0.5 * (lo + hi), lo, t_lo, hi, t_hi, true);
+                    return GF2_OK;
+                }
+                ++istep;
+                return next_interior();
+            }
+            default:
+                return fail(GF2_ESTATE, "mu search: not started");
+        }
+    }
+};
+
+// Returns mu and the number of evaluations; *slope is read (hint, <= 0 = none)
+// and replaced by the secant slope dN/dmu of the final bracket when known.
+static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const double *F,
+                   const double2 *Sig, double mu0, double *mu_out, int *evals_out,
+                   double *slope) {
+    if (d->nelec < 0 || d->nelec > 2 * c->n)
+        return fail(GF2_EBRACKET, "mu search: nelec outside [0, 2n]");
+    MuSearch ms;
+    ms.start(p, mu0, slope ? *slope : 0.0);
+    while (!ms.done) {
+        double f;
+        GF2_TRY(particle_excess(c, d, ms.pending, F, Sig, &f));
+        GF2_TRY(ms.feed(f));
+    }
+    if (ms.have_slope && slope) *slope = ms.slope;
+    *mu_out = ms.mu;
+    *evals_out = ms.evals;
+    return GF2_OK;
 }
 
 // One pass of 2.a-2.b without the Fock rebuild: mu, P_out, G(i w), moments, E_2b.
@@ -251,6 +334,100 @@ static int pulay_step(gf2_ctx *c, Pulay &pl, double *slots, size_t ne, const dou
     return GF2_OK;
 }
 
+// The inner loop (steps 2.a-2.b) of one system as a state machine.  Phase 0:
+// the mu search wants N(ms.pending) (a TRACE solve); phase 1: the density
+// pass wants a FULL (ENERGY when Sigma is set) solve at mu writing P_out,
+// G(i w) and the tail moments; phase 2: converged.  The single-system loop
+// and the batched driver feed it the same solves in the same order.
+struct InnerLoop {
+    gf2_ctx *c = nullptr;
+    const gf2_dims *d = nullptr;
+    const gf2_params *p = nullptr;
+    const double2 *Sig = nullptr;
+    const double *Sig1 = nullptr;
+    double *Pin = nullptr, *Pout = nullptr, *F = nullptr, *slots = nullptr, *r = nullptr;
+    double *mom = nullptr;
+    double2 *G_iw = nullptr;
+    Pulay pl;
+    MuSearch ms;
+    bool have_Pin = false;
+    double mu = 0.0, slope = 0.0, trPS = 0.0, e2b = 0.0;
+    int it = 0, n_inner = 0, n_eval = 0, phase = 0;
+
+    int density_mode() const { return Sig ? GF2_DYSON_ENERGY : GF2_DYSON_FULL; }
+
+    // workspaces and starting point (P from the state if present, F, mu)
+    int start(gf2_ctx *ctx, const gf2_dims *dd, const gf2_params *pp, const gf2_state *st,
+              const double2 *sig, const double *sig1) {
+        c = ctx; d = dd; p = pp; Sig = sig; Sig1 = sig1;
+        const size_t ne = (size_t)c->n * c->n;
+        GF2_TRY(c->it_Pout.ensure(ne * 8));
+        GF2_TRY(c->it_Pin.ensure(ne * 8));
+        GF2_TRY(c->it_F.ensure(ne * 8));
+        GF2_TRY(c->it_mom.ensure(3 * ne * 8));
+        GF2_TRY(c->it_G_iw.ensure((size_t)d->niw * ne * 16));
+        GF2_TRY(c->it_hist.ensure((size_t)2 * p->mix_depth * ne * 8));
+        GF2_TRY(c->it_tmp.ensure((1024 + 2 * ne) * 8));
+        Pin = c->it_Pin.as<double>();
+        Pout = c->it_Pout.as<double>();
+        F = c->it_F.as<double>();
+        mom = c->it_mom.as<double>();
+        G_iw = c->it_G_iw.as<double2>();
+        slots = c->it_hist.as<double>();
+        r = c->it_tmp.as<double>() + 1024 + ne;   // pulay_step uses [1024, 1024 + ne)
+        have_Pin = st->has_P != 0;
+        if (have_Pin) GF2_TRY(copy_d2d(c, Pin, st->P, ne * 8));
+        GF2_TRY(copy_d2d(c, F, st->F, ne * 8));
+        mu = st->mu;
+        slope = 0.0;
+        pl = Pulay();
+        pl.depth = p->mix_depth;
+        pl.B.assign((size_t)pl.depth * pl.depth, 0.0);
+        it = 1;
+        n_inner = n_eval = 0;
+        phase = 0;
+        ms.start(p, mu, slope);
+        return GF2_OK;
+    }
+    // result of the TRACE solve at ms.pending
+    int on_trace(double trps) {
+        GF2_TRY(ms.feed(trps - (double)d->nelec));
+        if (ms.done) {
+            mu = ms.mu;
+            if (ms.have_slope) slope = ms.slope;
+            phase = 1;
+        }
+        return GF2_OK;
+    }
+    // the density solve at mu has written Pout, G_iw and mom
+    int on_density(double trps, double e2) {
+        const size_t ne = (size_t)c->n * c->n;
+        trPS = trps;
+        e2b = e2;
+        n_eval += ms.evals;
+        n_inner = it;
+        if (!have_Pin) {
+            GF2_TRY(copy_d2d(c, Pin, Pout, ne * 8));
+            have_Pin = true;
+        } else {
+            double dmax;
+            GF2_TRY(max_abs_diff(c, ne, Pout, Pin, &dmax));
+            if (dmax < p->tol_P) {
+                phase = 2;
+                return GF2_OK;
+            }
+            GF2_TRY(copy_d2d(c, r, Pout, ne * 8));
+            GF2_TRY(axpby(c, ne, -1.0, Pin, 1.0, r));
+            GF2_TRY(pulay_step(c, pl, slots, ne, Pin, r, p->damp_P, Pin));
+        }
+        GF2_TRY(fock_run(c, Pin, F));
+        if (++it > p->max_inner) return fail(GF2_ENOCONV, "gf2_iterate: inner loop did not converge");
+        ms.start(p, mu, slope);
+        phase = 0;
+        return GF2_OK;
+    }
+};
+
 static int check_dims(gf2_ctx *c, const gf2_dims *d, const char *who) {
     if (!c || !d) return fail(GF2_EINVAL, std::string(who) + ": NULL argument");
     if (!c->has_system) return fail(GF2_ESTATE, std::string(who) + ": no system set");
@@ -312,128 +489,206 @@ extern "C" int gf2_density_fock(gf2_ctx *c, const gf2_dims *d, const gf2_params 
     return GF2_OK;
 }
 
-extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
-                           gf2_report *rep) {
-    GF2_TRY(check_dims(c, d, "gf2_iterate"));
-    GF2_TRY(check_params(p, "gf2_iterate"));
-    if (!st || !rep || !st->F || !st->P || !st->G_tau || !st->Sigma_tau)
-        return fail(GF2_EINVAL, "gf2_iterate: NULL state array or report");
-    GF2_HIP(hipSetDevice(c->device));
-    const double t0 = now_ms();
-    const int n = c->n;
-    const size_t ne = (size_t)n * n;
+namespace gf2 {
+
+// Steps 3 and the Sigma part of an outer iteration: Sigma(tau) from G(tau),
+// damping, Sigma(i w) and Sigma_1.  Iteration 0 (Hartree-Fock) has no Sigma.
+static int iter_sigma(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
+                      const double2 **Sig, const double **Sig1, double *t_sig, double *t_four) {
+    const size_t ne = (size_t)c->n * c->n;
     const size_t nt = (size_t)d->ntau * ne;
-    GF2_TRY(c->it_Pout.ensure(ne * 8));
-    GF2_TRY(c->it_Pin.ensure(ne * 8));
-    GF2_TRY(c->it_F.ensure(ne * 8));
-    GF2_TRY(c->it_mom.ensure(3 * ne * 8));
     GF2_TRY(c->it_Sig1.ensure(ne * 8));
-    GF2_TRY(c->it_G_iw.ensure((size_t)d->niw * ne * 16));
-    GF2_TRY(c->it_hist.ensure((size_t)2 * p->mix_depth * ne * 8));
-    GF2_TRY(c->it_tmp.ensure((1024 + ne) * 8));
+    *Sig = nullptr;
+    *Sig1 = nullptr;
+    if (st->iteration == 0) return GF2_OK;
+    GF2_TRY(c->it_Sig_new.ensure(nt * 8));
+    GF2_TRY(c->it_Sig_iw.ensure((size_t)d->niw * ne * 16));
+    double *Snew = c->it_Sig_new.as<double>();
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    const double ts = now_ms();
+    GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, Snew));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    *t_sig += now_ms() - ts;
+    int bad = 0;
+    GF2_TRY(any_nonfinite(c, nt, Snew, &bad));
+    if (bad) return fail(GF2_ENONFINITE, "gf2_iterate: non-finite self-energy");
+    if (st->iteration >= 2 && p->damp_Sigma > 0.0)
+        GF2_TRY(axpby(c, nt, p->damp_Sigma, st->Sigma_tau, 1.0 - p->damp_Sigma, Snew));
+    GF2_TRY(copy_d2d(c, st->Sigma_tau, Snew, nt * 8));
+    const double tf = now_ms();
+    GF2_TRY(fourier_tau2iw(c, d, st->Sigma_tau, c->it_Sig_iw.as<double2>(), c->it_Sig1.as<double>()));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    *t_four += now_ms() - tf;
+    *Sig = c->it_Sig_iw.as<double2>();
+    *Sig1 = c->it_Sig1.as<double>();
+    return GF2_OK;
+}
 
-    double t_sig = 0.0, t_four = 0.0;
-    const double2 *Sig = nullptr;
-    const double *Sig1 = nullptr;
-    if (st->iteration > 0) {
-        GF2_TRY(c->it_Sig_new.ensure(nt * 8));
-        GF2_TRY(c->it_Sig_iw.ensure((size_t)d->niw * ne * 16));
-        double *Snew = c->it_Sig_new.as<double>();
-        GF2_HIP(hipStreamSynchronize(c->stream));
-        const double ts = now_ms();
-        GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, Snew));
-        GF2_HIP(hipStreamSynchronize(c->stream));
-        t_sig = now_ms() - ts;
-        int bad = 0;
-        GF2_TRY(any_nonfinite(c, nt, Snew, &bad));
-        if (bad) return fail(GF2_ENONFINITE, "gf2_iterate: non-finite self-energy");
-        if (st->iteration >= 2 && p->damp_Sigma > 0.0)
-            GF2_TRY(axpby(c, nt, p->damp_Sigma, st->Sigma_tau, 1.0 - p->damp_Sigma, Snew));
-        GF2_TRY(copy_d2d(c, st->Sigma_tau, Snew, nt * 8));
-        const double tf = now_ms();
-        GF2_TRY(fourier_tau2iw(c, d, st->Sigma_tau, c->it_Sig_iw.as<double2>(),
-                               c->it_Sig1.as<double>()));
-        GF2_HIP(hipStreamSynchronize(c->stream));
-        t_four += now_ms() - tf;
-        Sig = c->it_Sig_iw.as<double2>();
-        Sig1 = c->it_Sig1.as<double>();
-    }
-
-    // ---- inner loop ----
-    const double ti = now_ms();
-    double *Pin = c->it_Pin.as<double>(), *Pout = c->it_Pout.as<double>(), *F = c->it_F.as<double>();
-    bool have_Pin = st->has_P != 0;
-    if (have_Pin) GF2_TRY(copy_d2d(c, Pin, st->P, ne * 8));
-    GF2_TRY(copy_d2d(c, F, st->F, ne * 8));
-    double mu = st->mu;
-    Pulay pl;
-    pl.depth = p->mix_depth;
-    pl.B.assign((size_t)pl.depth * pl.depth, 0.0);
-    double *slots = c->it_hist.as<double>();
-    double *r = c->it_tmp.as<double>() + 1024;   // residual; pulay_step uses its own tmp below
-    GF2_TRY(c->it_tmp.ensure((1024 + 2 * ne) * 8));
-    r = c->it_tmp.as<double>() + 1024 + ne;
-    int n_inner = 0, n_eval = 0;
-    double e2b = 0.0, trPS = 0.0;
-    double slope = 0.0;   // dN/dmu carried from one mu search to the next
-    bool converged = false;
-    for (int it = 1; it <= p->max_inner; ++it) {
-        int ev = 0;
-        GF2_TRY(density_pass(c, d, p, F, Sig, Sig1, &mu, Pout, c->it_G_iw.as<double2>(),
-                             c->it_mom.as<double>(), &trPS, &e2b, &ev, &slope));
-        n_eval += ev;
-        n_inner = it;
-        if (!have_Pin) {
-            GF2_TRY(copy_d2d(c, Pin, Pout, ne * 8));
-            have_Pin = true;
-        } else {
-            double dmax;
-            GF2_TRY(max_abs_diff(c, ne, Pout, Pin, &dmax));
-            if (dmax < p->tol_P) {
-                converged = true;
-                break;
-            }
-            GF2_TRY(copy_d2d(c, r, Pout, ne * 8));
-            GF2_TRY(axpby(c, ne, -1.0, Pin, 1.0, r));
-            GF2_TRY(pulay_step(c, pl, slots, ne, Pin, r, p->damp_P, Pin));
-        }
-        GF2_TRY(fock_run(c, Pin, F));
-    }
-    if (!converged) return fail(GF2_ENOCONV, "gf2_iterate: inner loop did not converge");
+// End of an outer iteration after the inner loop: F(P_out), E_1b, G(tau),
+// state update and report (ms_* filled by the caller).
+static int iter_finish(gf2_ctx *c, const gf2_dims *d, gf2_state *st, InnerLoop &il,
+                       gf2_report *rep, double *t_four) {
+    const size_t ne = (size_t)c->n * c->n;
+    double *Pout = il.Pout, *F = il.F;
     GF2_TRY(fock_run(c, Pout, F));
     double ph, pf;
     GF2_TRY(dot(c, ne, Pout, c->h.as<double>(), &ph));
     GF2_TRY(dot(c, ne, Pout, F, &pf));
     const double e1b = 0.5 * (ph + pf);
-    const double t_inner = now_ms() - ti;
-
-    // ---- G(tau) for the next Sigma ----
     const double tf2 = now_ms();
-    GF2_TRY(fourier_iw2tau(c, d, c->it_G_iw.as<double2>(), c->it_mom.as<double>(), st->G_tau));
+    GF2_TRY(fourier_iw2tau(c, d, il.G_iw, il.mom, st->G_tau));
     GF2_HIP(hipStreamSynchronize(c->stream));
-    t_four += now_ms() - tf2;
-
+    *t_four += now_ms() - tf2;
     double dP = INFINITY;
     if (st->has_P) GF2_TRY(max_abs_diff(c, ne, Pout, st->P, &dP));
     GF2_TRY(copy_d2d(c, st->P, Pout, ne * 8));
     GF2_TRY(copy_d2d(c, st->F, F, ne * 8));
     GF2_HIP(hipStreamSynchronize(c->stream));
-    const double E = e1b + e2b;
+    const double E = e1b + il.e2b;
     rep->energy = E;
     rep->e1b = e1b;
-    rep->e2b = e2b;
+    rep->e2b = il.e2b;
     rep->dE = std::isfinite(st->energy) ? E - st->energy : INFINITY;
     rep->dP = dP;
-    rep->mu = mu;
-    rep->n_inner = n_inner;
-    rep->n_eval = n_eval;
-    rep->ms_sigma = t_sig;
-    rep->ms_fourier = t_four;
-    rep->ms_inner = t_inner;
-    rep->ms_total = now_ms() - t0;
-    st->mu = mu;
+    rep->mu = il.mu;
+    rep->n_inner = il.n_inner;
+    rep->n_eval = il.n_eval;
+    st->mu = il.mu;
     st->energy = E;
     st->has_P = 1;
     st->iteration += 1;
+    return GF2_OK;
+}
+
+static int check_state(const gf2_state *st, const gf2_report *rep, const char *who) {
+    if (!st || !rep || !st->F || !st->P || !st->G_tau || !st->Sigma_tau)
+        return fail(GF2_EINVAL, std::string(who) + ": NULL state array or report");
+    return GF2_OK;
+}
+
+}  // namespace gf2
+
+extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
+                           gf2_report *rep) {
+    GF2_TRY(check_dims(c, d, "gf2_iterate"));
+    GF2_TRY(check_params(p, "gf2_iterate"));
+    GF2_TRY(check_state(st, rep, "gf2_iterate"));
+    GF2_HIP(hipSetDevice(c->device));
+    const double t0 = now_ms();
+    double t_sig = 0.0, t_four = 0.0;
+    const double2 *Sig = nullptr;
+    const double *Sig1 = nullptr;
+    GF2_TRY(iter_sigma(c, d, p, st, &Sig, &Sig1, &t_sig, &t_four));
+
+    const double ti = now_ms();
+    InnerLoop il;
+    GF2_TRY(il.start(c, d, p, st, Sig, Sig1));
+    while (il.phase != 2) {
+        double r2[2];
+        if (il.phase == 0) {
+            GF2_TRY(dyson_run(c, d, GF2_DYSON_TRACE, il.ms.pending, il.F, Sig, nullptr, nullptr,
+                              nullptr, nullptr, r2));
+            GF2_TRY(il.on_trace(r2[0]));
+        } else {
+            GF2_TRY(dyson_run(c, d, il.density_mode(), il.mu, il.F, Sig, Sig1, il.G_iw, il.Pout,
+                              il.mom, r2));
+            GF2_TRY(il.on_density(r2[0], r2[1]));
+        }
+    }
+    const double t_inner_end = now_ms();
+    GF2_TRY(iter_finish(c, d, st, il, rep, &t_four));
+    rep->ms_sigma = t_sig;
+    rep->ms_fourier = t_four;
+    rep->ms_inner = t_inner_end - ti;
+    rep->ms_total = now_ms() - t0;
+    return GF2_OK;
+}
+
+// Batched sweep: the inner loops of all systems advance in lockstep; every
+// round is one dyson_round over all systems that still need a solve.
+extern "C" int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
+                                   const gf2_params *p, gf2_state *states, gf2_report *reps) {
+    if (!ctxs || nsys < 1 || !dims || !states || !reps)
+        return fail(GF2_EINVAL, "gf2_iterate_batched: NULL argument or nsys < 1");
+    GF2_TRY(check_params(p, "gf2_iterate_batched"));
+    gf2_ctx *lead = ctxs[0];
+    for (int s = 0; s < nsys; ++s) {
+        GF2_TRY(check_dims(ctxs[s], &dims[s], "gf2_iterate_batched"));
+        GF2_TRY(check_state(&states[s], &reps[s], "gf2_iterate_batched"));
+        if (ctxs[s]->device != lead->device)
+            return fail(GF2_EINVAL, "gf2_iterate_batched: contexts on different devices");
+        for (int t = 0; t < s; ++t)
+            if (ctxs[t] == ctxs[s]) return fail(GF2_EINVAL, "gf2_iterate_batched: context repeated");
+    }
+    GF2_HIP(hipSetDevice(lead->device));
+    // everything runs on the lead context's stream
+    struct StreamSwap {
+        std::vector<hipStream_t> saved;
+        gf2_ctx *const *cs;
+        int ns;
+        ~StreamSwap() {
+            for (int s = 0; s < ns; ++s) cs[s]->stream = saved[s];
+        }
+    } swap{std::vector<hipStream_t>(nsys), ctxs, nsys};
+    for (int s = 0; s < nsys; ++s) {
+        swap.saved[s] = ctxs[s]->stream;
+        GF2_HIP(hipStreamSynchronize(ctxs[s]->stream));
+    }
+    for (int s = 0; s < nsys; ++s) ctxs[s]->stream = lead->stream;
+
+    const double t0 = now_ms();
+    double t_sig = 0.0, t_four = 0.0;
+    std::vector<const double2 *> Sig(nsys);
+    std::vector<const double *> Sig1(nsys);
+    for (int s = 0; s < nsys; ++s)
+        GF2_TRY(iter_sigma(ctxs[s], &dims[s], p, &states[s], &Sig[s], &Sig1[s], &t_sig, &t_four));
+
+    const double ti = now_ms();
+    std::vector<InnerLoop> il(nsys);
+    for (int s = 0; s < nsys; ++s)
+        GF2_TRY(il[s].start(ctxs[s], &dims[s], p, &states[s], Sig[s], Sig1[s]));
+    std::vector<DysonReq> req(nsys);
+    std::vector<double> res;
+    for (;;) {
+        bool any = false;
+        for (int s = 0; s < nsys; ++s) {
+            DysonReq &q = req[s];
+            q = DysonReq{};
+            q.c = ctxs[s];
+            q.d = &dims[s];
+            q.F = il[s].F;
+            q.Sig = Sig[s];
+            if (il[s].phase == 0) {
+                q.mode = GF2_DYSON_TRACE;
+                q.mu = il[s].ms.pending;
+                any = true;
+            } else if (il[s].phase == 1) {
+                q.mode = il[s].density_mode();
+                q.mu = il[s].mu;
+                q.Sig1 = Sig1[s];
+                q.G_iw = il[s].G_iw;
+                q.P = il[s].Pout;
+                q.mom = il[s].mom;
+                any = true;
+            } else {
+                q.mode = -1;
+            }
+        }
+        if (!any) break;
+        GF2_TRY(dyson_round(lead, req, res));
+        for (int s = 0; s < nsys; ++s) {
+            if (req[s].mode == GF2_DYSON_TRACE) GF2_TRY(il[s].on_trace(res[2 * s]));
+            else if (req[s].mode > GF2_DYSON_TRACE) GF2_TRY(il[s].on_density(res[2 * s], res[2 * s + 1]));
+        }
+    }
+    const double t_inner = now_ms() - ti;
+    for (int s = 0; s < nsys; ++s) GF2_TRY(iter_finish(ctxs[s], &dims[s], &states[s], il[s], &reps[s], &t_four));
+    const double t_total = now_ms() - t0;
+    for (int s = 0; s < nsys; ++s) {
+        reps[s].ms_sigma = t_sig;
+        reps[s].ms_fourier = t_four;
+        reps[s].ms_inner = t_inner;
+        reps[s].ms_total = t_total;
+    }
     return GF2_OK;
 }

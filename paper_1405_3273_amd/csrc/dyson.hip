@@ -28,16 +28,37 @@ constexpr int DY_TR = 16;          // threads per column
 constexpr int DY_MAXN = 160;
 constexpr int DY_MAXTHREADS = 512;
 
-struct DysonArgs {
-    int n, niw, mode;
+// One system's Dyson evaluation.  The single-system call passes one job by
+// value; the batched driver passes a device table of jobs (one per system)
+// and the block offsets of each system in the launch.  Every kernel below
+// resolves its job the same way, so a system gets identical arithmetic in
+// both cases.
+struct DysonJob {
+    int n, niw, mode;       // mode < 0: idle (batched rounds)
+    int p_in_lds;           // FULL/ENERGY: accumulate P in LDS (else in partP directly)
+    int nbl;                // workgroups of this job in the Dyson launch
     double beta, mu;
-    const double *S, *F, *G2;
+    const double *S, *Sinv, *F, *Sig1;   // Sig1 may be NULL
     const double2 *Sig;     // may be NULL
     double2 *G;             // may be NULL
-    double *partP;          // [gridDim.x][n*n]   (FULL/ENERGY)
-    double *parts;          // [gridDim.x][4]     (trace, energy, singular flag)
-    int p_in_lds;           // FULL/ENERGY: accumulate P in LDS (else in partP directly)
+    double *P;              // FULL/ENERGY output
+    double *mom;            // [3][n][n] tail moments G1, G2, G3 (computed here)
+    double *scr;            // [3][n][n] scratch
+    double *partP;          // [nbl][n*n]   (FULL/ENERGY)
+    double *parts;          // [nbl][4]     (trace, energy, singular flag)
+    double *out;            // [5] reduced results
 };
+
+struct DysonRef {
+    DysonJob one;           // used when nsys == 0
+    const DysonJob *tab;    // [nsys]
+    const int *boff;        // [nsys + 1] first Dyson workgroup of each job
+    int nsys;
+};
+
+__device__ __forceinline__ DysonJob job_of(const DysonRef &g, int s) {
+    return g.nsys == 0 ? g.one : g.tab[s];
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -78,8 +99,9 @@ template <int K> __device__ __forceinline__ void argmax_step(double &best, int &
     bi = take ? oi : bi;
 }
 
+// lb: this workgroup's index among the nbl workgroups of its job
 template <int RA, int CB, int TC>
-__global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
+__device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, const int nbl) {
     const int n = a.n;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -96,7 +118,7 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
     extern __shared__ double shP[];   // n*n when FULL/ENERGY and p_in_lds
 
     const bool full = a.mode != GF2_DYSON_TRACE;
-    double *Pacc = a.p_in_lds ? shP : (a.partP + (size_t)blockIdx.x * n * n);
+    double *Pacc = a.p_in_lds ? shP : (a.partP + (size_t)lb * n * n);
     if (full)
         for (int e = tid; e < n * n; e += nthr) Pacc[e] = 0.0;
     if (tid == 0) sing = 0;
@@ -104,7 +126,7 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
     double acc_tr = 0.0, acc_e = 0.0;
     double mr[RA][CB], mi[RA][CB];
 
-    for (int nn = blockIdx.x; nn < a.niw; nn += gridDim.x) {
+    for (int nn = lb; nn < a.niw; nn += nbl) {
         const double w = M_PI * (double)(2 * nn + 1) / a.beta;
         const double2 *Sig = a.Sig ? a.Sig + (size_t)nn * n * n : nullptr;
         // The element addresses do not depend on nn; hiding the bases from the
@@ -242,7 +264,7 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
                 if (!full) {
                     acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
                 } else {
-                    Pacc[e] += mr[ia][jb] + a.G2[e] * iw2;
+                    Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
                     if (a.mode == GF2_DYSON_ENERGY && Sig) {
                         const double2 sg = Sig[(size_t)gb * n + ga];
@@ -273,7 +295,7 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
                 s0 += red[0][t];
                 s1 += red[1][t];
             }
-            double *ps = a.parts + (size_t)blockIdx.x * 4;
+            double *ps = a.parts + (size_t)lb * 4;
             ps[0] = s0;
             ps[1] = s1;
             ps[2] = (double)sing;
@@ -281,38 +303,93 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonArgs a) {
         }
     }
     if (full && a.p_in_lds)
-        for (int e = tid; e < n * n; e += nthr) a.partP[(size_t)blockIdx.x * n * n + e] = shP[e];
+        for (int e = tid; e < n * n; e += nthr) a.partP[(size_t)lb * n * n + e] = shP[e];
 }
 
-// P = (4/beta) sum_b partP[b] + G1 - (beta/2) G2
-__global__ void k_reduce_P(int ne, int nb, double beta, const double *__restrict__ partP,
-                           const double *__restrict__ G1, const double *__restrict__ G2,
-                           double *__restrict__ P) {
+// GRP: the jobs come from the table (batched launch), else the job is the
+// kernel argument itself (its fields stay reloadable kernel-argument reads).
+template <int RA, int CB, int TC, bool GRP>
+__global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonRef g) {
+    if constexpr (GRP) {
+        int sys = 0;
+        while (sys + 1 < g.nsys && g.boff[sys + 1] <= (int)blockIdx.x) ++sys;
+        sys = __builtin_amdgcn_readfirstlane(sys);
+        const DysonJob a = g.tab[sys];
+        if (a.mode < 0) return;
+        dyson_body<RA, CB, TC>(a, (int)blockIdx.x - g.boff[sys], a.nbl);
+    } else {
+        dyson_body<RA, CB, TC>(g.one, (int)blockIdx.x, (int)gridDim.x);
+    }
+}
+
+// Tail moments of every job (one workgroup per job):
+// G1 = Sinv, G2 = Sinv H Sinv, G3 = Sinv H G2 (+ Sinv Sig1 Sinv in FULL/ENERGY),
+// H = F - mu S.  Products in the order of a plain row-by-column sum.
+__device__ void block_matmul(int n, const double *A, const double *B, double *C) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+        C[e] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_moments(DysonRef g) {
+    const DysonJob a = job_of(g, blockIdx.x);
+    if (a.mode < 0) return;
+    const int n = a.n, ne = n * n;
+    double *H = a.scr, *Y = a.scr + ne, *Z = a.scr + 2 * ne;
+    double *G1 = a.mom, *G2 = a.mom + ne, *G3 = a.mom + 2 * ne;
+    const double b1 = 1.0, am = -a.mu;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        H[e] = am * a.S[e] + b1 * a.F[e];
+        G1[e] = a.Sinv[e];
+    }
+    __syncthreads();
+    block_matmul(n, a.Sinv, H, Y);   // Sinv H
+    block_matmul(n, Y, a.Sinv, G2);  // G2
+    block_matmul(n, Y, G2, G3);      // Sinv H G2
+    if (a.mode != GF2_DYSON_TRACE && a.Sig1) {
+        block_matmul(n, a.Sinv, a.Sig1, Z);
+        block_matmul(n, Z, a.Sinv, H);
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) G3[e] = b1 * H[e] + b1 * G3[e];
+    }
+}
+
+// P = (4/beta) sum_b partP[b] + G1 - (beta/2) G2   (grid: x over elements, y over jobs)
+__global__ void k_reduce_P(DysonRef g) {
+    const DysonJob a = job_of(g, blockIdx.y);
+    if (a.mode <= GF2_DYSON_TRACE) return;
+    const int ne = a.n * a.n;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partP[(size_t)b * ne + e];
-    P[e] = (4.0 / beta) * s + G1[e] - 0.5 * beta * G2[e];
+    for (int b = 0; b < a.nbl; ++b) s += a.partP[(size_t)b * ne + e];
+    a.P[e] = (4.0 / a.beta) * s + a.mom[e] - 0.5 * a.beta * a.mom[ne + e];
 }
 
 // out[0] = sum_b parts[b][0], out[1] = sum parts[b][1], out[2] = max flag,
-// out[3] = <X, Y> (Frobenius), out[4] = <U, V>
-__global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict__ parts, int ne,
-                                                const double *__restrict__ X,
-                                                const double *__restrict__ Y,
-                                                const double *__restrict__ U,
-                                                const double *__restrict__ V,
-                                                double *__restrict__ out) {
+// out[3] = <X, Y> (Frobenius), out[4] = <U, V>; TRACE: X = G2, Y = S;
+// FULL/ENERGY: X = P, Y = S, U = G1, V = Sig1 (ENERGY with Sig1).  One workgroup per job.
+__global__ __launch_bounds__(256) void k_finish(DysonRef g) {
+    const DysonJob a = job_of(g, blockIdx.x);
+    if (a.mode < 0) return;
+    const int ne = a.n * a.n;
+    const bool full = a.mode != GF2_DYSON_TRACE;
+    const double *X = full ? a.P : a.mom + ne;
+    const double *Y = a.S;
+    const double *U = (a.mode == GF2_DYSON_ENERGY && a.Sig1) ? a.mom : nullptr;
+    const double *V = a.Sig1;
     __shared__ double sh[5][256];
     const int t = threadIdx.x;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
-    for (int b = t; b < nb; b += 256) {
-        a0 += parts[(size_t)b * 4];
-        a1 += parts[(size_t)b * 4 + 1];
-        a2 = fmax(a2, parts[(size_t)b * 4 + 2]);
+    for (int b = t; b < a.nbl; b += 256) {
+        a0 += a.parts[(size_t)b * 4];
+        a1 += a.parts[(size_t)b * 4 + 1];
+        a2 = fmax(a2, a.parts[(size_t)b * 4 + 2]);
     }
-    if (X && Y)
-        for (int e = t; e < ne; e += 256) a3 += X[e] * Y[e];
+    for (int e = t; e < ne; e += 256) a3 += X[e] * Y[e];
     if (U && V)
         for (int e = t; e < ne; e += 256) a4 += U[e] * V[e];
     sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = a3; sh[4][t] = a4;
@@ -327,36 +404,79 @@ __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict
         }
         __syncthreads();
     }
-    if (t < 5) out[t] = sh[t][0];
+    if (t < 5) a.out[t] = sh[t][0];
 }
 
+// attr_only: set the dynamic-LDS limit without launching (before a capture)
 template <int RA, int CB, int TC>
-static int launch_dyson(dim3 grid, size_t shm, hipStream_t s, const DysonArgs &a) {
-    if (shm > 0)
-        GF2_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dyson<RA, CB, TC>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL((k_dyson<RA, CB, TC>), grid, dim3(DY_TR * TC), shm, s, a);
+static int launch_dyson(dim3 grid, size_t shm, hipStream_t s, const DysonRef &g,
+                        bool attr_only = false) {
+    const void *fn = (g.nsys > 0) ? reinterpret_cast<const void *>(&k_dyson<RA, CB, TC, true>)
+                                  : reinterpret_cast<const void *>(&k_dyson<RA, CB, TC, false>);
+    if (shm > 0) GF2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    if (attr_only) return GF2_OK;
+    if (g.nsys > 0)
+        hipLaunchKernelGGL((k_dyson<RA, CB, TC, true>), grid, dim3(DY_TR * TC), shm, s, g);
+    else
+        hipLaunchKernelGGL((k_dyson<RA, CB, TC, false>), grid, dim3(DY_TR * TC), shm, s, g);
     return GF2_OK;
 }
 
-// Tail moments on the device: G1 = Sinv, G2 = Sinv H Sinv, G3 = Sinv H G2 + Sinv Sig1 Sinv,
-// H = F - mu S.  Writes mom[0..2]; scratch: 3 n x n.
-static int moments(gf2_ctx *c, double mu, const double *F, const double *Sig1, double *mom,
-                   double *scratch) {
-    const int n = c->n;
-    const size_t ne = (size_t)n * n;
-    double *H = scratch, *Y = scratch + ne, *Z = scratch + 2 * ne;
-    GF2_TRY(copy_d2d(c, H, F, ne * 8));
-    GF2_TRY(axpby(c, ne, -mu, c->S.as<double>(), 1.0, H));
-    GF2_TRY(copy_d2d(c, mom, c->Sinv.ptr, ne * 8));
-    GF2_TRY(matmul_nn(c, n, c->Sinv.as<double>(), H, Y));          // Sinv H
-    GF2_TRY(matmul_nn(c, n, Y, c->Sinv.as<double>(), mom + ne));   // G2
-    GF2_TRY(matmul_nn(c, n, Y, mom + ne, mom + 2 * ne));           // Sinv H G2
-    if (Sig1) {
-        GF2_TRY(matmul_nn(c, n, c->Sinv.as<double>(), Sig1, Z));
-        GF2_TRY(matmul_nn(c, n, Z, c->Sinv.as<double>(), H));
-        GF2_TRY(axpby(c, ne, 1.0, H, 1.0, mom + 2 * ne));
+// Size class of the register-resident inverse (rows per thread)
+static int dyson_class(int n) { return (n + DY_TR - 1) / DY_TR; }
+
+static int launch_dyson_class(int ra, dim3 grid, size_t shm, hipStream_t s, const DysonRef &g,
+                              bool attr_only = false) {
+    switch (ra) {
+        case 1: return launch_dyson<1, 1, 16>(grid, shm, s, g, attr_only);
+        case 2: return launch_dyson<2, 2, 16>(grid, shm, s, g, attr_only);
+        case 3: return launch_dyson<3, 3, 16>(grid, shm, s, g, attr_only);
+        case 4: return launch_dyson<4, 4, 16>(grid, shm, s, g, attr_only);
+        case 5: return launch_dyson<5, 5, 16>(grid, shm, s, g, attr_only);
+        case 6: return launch_dyson<6, 6, 16>(grid, shm, s, g, attr_only);
+        case 7: return launch_dyson<7, 7, 16>(grid, shm, s, g, attr_only);
+        case 8: return launch_dyson<8, 4, 32>(grid, shm, s, g, attr_only);
+        case 9: return launch_dyson<9, 5, 32>(grid, shm, s, g, attr_only);
+        default: return launch_dyson<10, 5, 32>(grid, shm, s, g, attr_only);
     }
+}
+
+// Workgroups per job: two resident per CU give each a partner to overlap
+// barriers with; LDS P accumulation only while it keeps that.
+static int dyson_blocks(gf2_ctx *c, int niw) {
+    int dev_cus = 256;
+    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    return std::max(1, std::min(niw, 2 * dev_cus));
+}
+static bool dyson_p_in_lds(int n, int mode) {
+    return mode != GF2_DYSON_TRACE && (size_t)n * n * 8 <= 32 * 1024;
+}
+
+// Host part of a job's result: h = out[0..4] of k_finish
+static int dyson_post(const DysonJob &j, const double *h, double *out) {
+    if (h[2] != 0.0) return fail(GF2_ENONFINITE, "gf2_dyson: singular or non-finite matrix");
+    const double beta = j.beta;
+    if (j.mode != GF2_DYSON_TRACE) {
+        out[0] = h[3];
+        out[1] = 0.0;
+        if (j.mode == GF2_DYSON_ENERGY && j.Sig) {
+            const double tg = h[4];
+            const double tail = -(2.0 / beta) * tg * (beta / (2.0 * M_PI)) * (beta / (2.0 * M_PI)) *
+                                trigamma(j.niw + 0.5);
+            out[1] = (2.0 / beta) * h[1] + tail;
+        }
+    } else {
+        double sw = 0.0;   // sum_{n<niw} 1/w_n^2
+        for (int k = 0; k < j.niw; ++k) {
+            const double w = M_PI * (double)(2 * k + 1) / beta;
+            sw += 1.0 / (w * w);
+        }
+        const double trG2S = h[3];
+        out[0] = (4.0 / beta) * (h[0] + trG2S * sw) + (double)j.n - 0.5 * beta * trG2S;
+        out[1] = 0.0;
+    }
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+        return fail(GF2_ENONFINITE, "gf2_dyson: non-finite result");
     return GF2_OK;
 }
 
@@ -366,90 +486,254 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     const int n = c->n, niw = d->niw;
     const size_t ne = (size_t)n * n;
     if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
-    const int RA = (n + DY_TR - 1) / DY_TR;
     const bool full = mode != GF2_DYSON_TRACE;
-    // a large LDS accumulator would keep a second workgroup off the CU
-    const bool p_in_lds = full && ne * 8 <= 32 * 1024;
+    const int nblocks = dyson_blocks(c, niw);
+    const bool p_in_lds = dyson_p_in_lds(n, mode);
     const size_t shm = p_in_lds ? ne * 8 : 0;
-    int dev_cus = 256;
-    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    // two resident workgroups per CU give each one a partner to overlap barriers with
-    const int nblocks = std::max(1, std::min(niw, 2 * dev_cus));
 
     GF2_TRY(c->dys_X.ensure(6 * ne * 8));
     GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
     GF2_TRY(c->dys_out.ensure(8 * 8));
     if (full) GF2_TRY(c->dys_part.ensure((size_t)nblocks * ne * 8));
-    double *mom = c->dys_X.as<double>();          // [3][n][n]
-    double *scr = mom + 3 * ne;                    // [3][n][n]
-    GF2_TRY(moments(c, mu, F, (mode == GF2_DYSON_TRACE) ? nullptr : Sig1, mom, scr));
 
-    DysonArgs a{};
+    DysonRef g{};
+    DysonJob &a = g.one;
     a.n = n; a.niw = niw; a.mode = mode;
+    a.p_in_lds = p_in_lds ? 1 : 0;
+    a.nbl = nblocks;
     a.beta = d->beta; a.mu = mu;
-    a.S = c->S.as<double>(); a.F = F; a.G2 = mom + ne;
+    a.S = c->S.as<double>(); a.Sinv = c->Sinv.as<double>(); a.F = F;
+    a.Sig1 = full ? Sig1 : nullptr;
     a.Sig = Sig_iw; a.G = full ? G_iw : nullptr;
+    a.P = full ? P : nullptr;
+    a.mom = c->dys_X.as<double>();
+    a.scr = a.mom + 3 * ne;
     a.partP = full ? c->dys_part.as<double>() : nullptr;
     a.parts = c->dys_aux.as<double>();
-    a.p_in_lds = p_in_lds ? 1 : 0;
-    dim3 grid(nblocks);
+    a.out = c->dys_out.as<double>();
+    g.nsys = 0;
+
+    hipLaunchKernelGGL(k_moments, dim3(1), dim3(256), 0, c->stream, g);
     const int ph = prof_begin(c, GF2_KC_DYSON);
-    switch (RA) {
-        case 1: GF2_TRY((launch_dyson<1, 1, 16>(grid, shm, c->stream, a))); break;
-        case 2: GF2_TRY((launch_dyson<2, 2, 16>(grid, shm, c->stream, a))); break;
-        case 3: GF2_TRY((launch_dyson<3, 3, 16>(grid, shm, c->stream, a))); break;
-        case 4: GF2_TRY((launch_dyson<4, 4, 16>(grid, shm, c->stream, a))); break;
-        case 5: GF2_TRY((launch_dyson<5, 5, 16>(grid, shm, c->stream, a))); break;
-        case 6: GF2_TRY((launch_dyson<6, 6, 16>(grid, shm, c->stream, a))); break;
-        case 7: GF2_TRY((launch_dyson<7, 7, 16>(grid, shm, c->stream, a))); break;
-        case 8: GF2_TRY((launch_dyson<8, 4, 32>(grid, shm, c->stream, a))); break;
-        case 9: GF2_TRY((launch_dyson<9, 5, 32>(grid, shm, c->stream, a))); break;
-        default: GF2_TRY((launch_dyson<10, 5, 32>(grid, shm, c->stream, a))); break;
-    }
+    GF2_TRY(launch_dyson_class(dyson_class(n), dim3(nblocks), shm, c->stream, g));
     prof_end(c, ph, 8.0 * (double)n * n * n * niw);
     GF2_HIP(hipGetLastError());
-
-    double *dout = c->dys_out.as<double>();
-    if (full) {
-        hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c->stream,
-                           (int)ne, nblocks, d->beta, c->dys_part.as<double>(), mom, mom + ne, P);
-        // out: [0] sum tr (unused), [1] sum Re tr(G Sigma), [2] flag, [3] tr(P S), [4] tr(G1 Sigma1)
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, nblocks, a.parts, (int)ne,
-                           P, c->S.as<double>(), (mode == GF2_DYSON_ENERGY && Sig1) ? mom : nullptr,
-                           Sig1, dout);
-    } else {
-        // out: [0] sum Re tr(G S), [3] tr(G2 S)
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, nblocks, a.parts, (int)ne,
-                           mom + ne, c->S.as<double>(), nullptr, nullptr, dout);
-    }
+    if (full)
+        hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((ne + 255) / 256), 1), dim3(256), 0,
+                           c->stream, g);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, g);
     GF2_HIP(hipGetLastError());
-    if (mom_out) GF2_TRY(copy_d2d(c, mom_out, mom, 3 * ne * 8));
+    if (mom_out) GF2_TRY(copy_d2d(c, mom_out, a.mom, 3 * ne * 8));
     double h[5];
-    GF2_HIP(hipMemcpyAsync(h, dout, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GF2_HIP(hipMemcpyAsync(h, a.out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     GF2_HIP(hipStreamSynchronize(c->stream));
-    if (h[2] != 0.0) return fail(GF2_ENONFINITE, "gf2_dyson: singular or non-finite matrix");
-    const double beta = d->beta;
-    if (full) {
-        out[0] = h[3];
-        out[1] = 0.0;
-        if (mode == GF2_DYSON_ENERGY && Sig_iw) {
-            const double tg = h[4];
-            const double tail = -(2.0 / beta) * tg * (beta / (2.0 * M_PI)) * (beta / (2.0 * M_PI)) *
-                                trigamma(niw + 0.5);
-            out[1] = (2.0 / beta) * h[1] + tail;
-        }
-    } else {
-        double sw = 0.0;   // sum_{n<niw} 1/w_n^2
-        for (int k = 0; k < niw; ++k) {
-            const double w = M_PI * (double)(2 * k + 1) / beta;
-            sw += 1.0 / (w * w);
-        }
-        const double trG2S = h[3];
-        out[0] = (4.0 / beta) * (h[0] + trG2S * sw) + (double)n - 0.5 * beta * trG2S;
-        out[1] = 0.0;
+    return dyson_post(a, h, out);
+}
+
+// ---------------------------------------------------------------------------
+// Batched rounds.  The jobs of all systems sit in one device table ordered by
+// size class; the round is k_moments (all jobs), one k_dyson per size class,
+// k_reduce_P and k_finish (all jobs).  That sequence is captured once into a
+// HIP graph per batch shape and replayed every round after the table upload.
+// Each job gets as many workgroups as dyson_run gives it, so its arithmetic
+// (and rounding) equals the single-system call.
+
+struct RoundShape {
+    std::vector<int> order;        // table position -> request index
+    std::vector<int> cls_begin;    // per class: first table position (size = ncls + 1)
+    std::vector<int> cls_ra;       // per class: rows per thread
+    std::vector<int> boff;         // per class: block offsets, concatenated (class c at cls_begin[c] + c)
+    std::vector<size_t> shm;       // per class dynamic LDS
+    long long key = 0;
+};
+
+static void release_graph(gf2_ctx *lead) {
+    if (lead->bat_graph) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(lead->bat_graph));
+        lead->bat_graph = nullptr;
     }
-    if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
-        return fail(GF2_ENONFINITE, "gf2_dyson: non-finite result");
+    lead->bat_key = 0;
+}
+
+void dyson_round_release(gf2_ctx *lead) {
+    release_graph(lead);
+    if (lead->bat_cap) {
+        (void)hipStreamDestroy(lead->bat_cap);
+        lead->bat_cap = nullptr;
+    }
+    if (lead->bat_host) {
+        (void)hipHostFree(lead->bat_host);
+        lead->bat_host = nullptr;
+        lead->bat_host_bytes = 0;
+    }
+}
+
+static int enqueue_round(gf2_ctx *lead, hipStream_t st, const RoundShape &sh, int nsys) {
+    const DysonJob *tab = lead->bat_tab.as<DysonJob>();
+    const int *boff = lead->bat_boff.as<int>();
+    DysonRef all{};
+    all.tab = tab;
+    all.nsys = nsys;
+    hipLaunchKernelGGL(k_moments, dim3(nsys), dim3(256), 0, st, all);
+    const int ncls = (int)sh.cls_ra.size();
+    for (int k = 0; k < ncls; ++k) {
+        DysonRef g{};
+        g.tab = tab + sh.cls_begin[k];
+        g.nsys = sh.cls_begin[k + 1] - sh.cls_begin[k];
+        g.boff = boff + sh.cls_begin[k] + k;
+        const int nblk = sh.boff[sh.cls_begin[k + 1] + k];
+        GF2_TRY(launch_dyson_class(sh.cls_ra[k], dim3(nblk), sh.shm[k], st, g));
+    }
+    int maxne = 1;
+    for (int k = 0; k < ncls; ++k) maxne = std::max(maxne, 16 * sh.cls_ra[k] * 16 * sh.cls_ra[k]);
+    hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((maxne + 255) / 256), (unsigned)nsys), dim3(256),
+                       0, st, all);
+    hipLaunchKernelGGL(k_finish, dim3(nsys), dim3(256), 0, st, all);
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<double> &res) {
+    const int nsys = (int)req.size();
+    res.assign((size_t)2 * nsys, 0.0);
+    // shape: systems ordered by size class (stable), workgroups per job
+    RoundShape sh;
+    std::vector<int> ra(nsys), nbl(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        if (req[s].c->n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
+        ra[s] = dyson_class(req[s].c->n);
+        nbl[s] = dyson_blocks(req[s].c, req[s].d->niw);
+    }
+    long long key = nsys;
+    for (int r = 1; r <= 10; ++r) {
+        bool any = false;
+        for (int s = 0; s < nsys; ++s)
+            if (ra[s] == r) {
+                if (!any) {
+                    sh.cls_begin.push_back((int)sh.order.size());
+                    sh.cls_ra.push_back(r);
+                    any = true;
+                }
+                sh.order.push_back(s);
+            }
+    }
+    sh.cls_begin.push_back(nsys);
+    const int ncls = (int)sh.cls_ra.size();
+    for (int k = 0; k < ncls; ++k) {
+        int acc = 0;
+        size_t shm = 0;
+        for (int t = sh.cls_begin[k]; t < sh.cls_begin[k + 1]; ++t) {
+            const int s = sh.order[t];
+            sh.boff.push_back(acc);
+            acc += nbl[s];
+            const size_t ne = (size_t)req[s].c->n * req[s].c->n;
+            if (dyson_p_in_lds(req[s].c->n, GF2_DYSON_FULL)) shm = std::max(shm, ne * 8);
+            key = key * 1000003LL + (long long)req[s].c->n * 7919 + nbl[s];
+        }
+        sh.boff.push_back(acc);
+        sh.shm.push_back(shm);
+    }
+    // per-job workspaces (each system's own context)
+    for (int s = 0; s < nsys; ++s) {
+        gf2_ctx *c = req[s].c;
+        const size_t ne = (size_t)c->n * c->n;
+        GF2_TRY(c->dys_X.ensure(6 * ne * 8));
+        GF2_TRY(c->dys_aux.ensure((size_t)nbl[s] * 4 * 8 + 64));
+        GF2_TRY(c->dys_part.ensure((size_t)nbl[s] * ne * 8));
+    }
+    const size_t tab_bytes = (size_t)nsys * sizeof(DysonJob);
+    const size_t boff_bytes = sh.boff.size() * sizeof(int);
+    GF2_TRY(lead->bat_tab.ensure(tab_bytes));
+    GF2_TRY(lead->bat_boff.ensure(boff_bytes));
+    GF2_TRY(lead->bat_out.ensure((size_t)nsys * 8 * 8));
+    // the captured graph holds these addresses
+    key = key * 1000003LL + (long long)(uintptr_t)lead->bat_tab.ptr;
+    key = key * 1000003LL + (long long)(uintptr_t)lead->bat_boff.ptr;
+    const size_t host_need = tab_bytes + (size_t)nsys * 8 * 8 + 64;
+    if (lead->bat_host_bytes < host_need) {
+        if (lead->bat_host) GF2_HIP(hipHostFree(lead->bat_host));
+        lead->bat_host = nullptr;
+        lead->bat_host_bytes = 0;
+        GF2_HIP(hipHostMalloc(&lead->bat_host, host_need, hipHostMallocDefault));
+        lead->bat_host_bytes = host_need;
+    }
+    DysonJob *tab_h = static_cast<DysonJob *>(lead->bat_host);
+    double *out_h = reinterpret_cast<double *>(static_cast<char *>(lead->bat_host) + tab_bytes);
+    double *out_d = lead->bat_out.as<double>();
+    for (int t = 0; t < nsys; ++t) {
+        const int s = sh.order[t];
+        const DysonReq &q = req[s];
+        gf2_ctx *c = q.c;
+        const int n = c->n;
+        const size_t ne = (size_t)n * n;
+        DysonJob a{};
+        a.n = n;
+        a.niw = q.d->niw;
+        a.mode = q.mode;
+        a.p_in_lds = dyson_p_in_lds(n, q.mode) ? 1 : 0;
+        a.nbl = nbl[s];
+        a.beta = q.d->beta;
+        a.mu = q.mu;
+        a.S = c->S.as<double>();
+        a.Sinv = c->Sinv.as<double>();
+        a.F = q.F;
+        const bool full = q.mode > GF2_DYSON_TRACE;
+        a.Sig1 = full ? q.Sig1 : nullptr;
+        a.Sig = q.Sig;
+        a.G = full ? q.G_iw : nullptr;
+        a.P = full ? q.P : nullptr;
+        a.mom = (full && q.mom) ? q.mom : c->dys_X.as<double>();
+        a.scr = c->dys_X.as<double>() + 3 * ne;
+        a.partP = c->dys_part.as<double>();
+        a.parts = c->dys_aux.as<double>();
+        a.out = out_d + (size_t)t * 8;
+        tab_h[t] = a;
+    }
+    GF2_HIP(hipMemcpyAsync(lead->bat_tab.ptr, tab_h, tab_bytes, hipMemcpyHostToDevice, lead->stream));
+    // (re)capture the round when the shape changed; the upload above is not part of it
+    if (!lead->bat_graph || lead->bat_key != key) {
+        release_graph(lead);
+        GF2_HIP(hipMemcpyAsync(lead->bat_boff.ptr, sh.boff.data(), boff_bytes,
+                               hipMemcpyHostToDevice, lead->stream));
+        for (int k = 0; k < ncls; ++k)   // attributes are set outside the capture
+            if (sh.shm[k] > 0) {
+                DysonRef g{};
+                g.nsys = 1;
+                GF2_TRY(launch_dyson_class(sh.cls_ra[k], dim3(1), sh.shm[k], lead->stream, g, true));
+            }
+        GF2_HIP(hipStreamSynchronize(lead->stream));
+        // capture on a private stream (the caller's may be the legacy default
+        // stream, which cannot be captured); the graph is launched on the caller's
+        if (!lead->bat_cap) GF2_HIP(hipStreamCreateWithFlags(&lead->bat_cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        GF2_HIP(hipStreamBeginCapture(lead->bat_cap, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_round(lead, lead->bat_cap, sh, nsys);
+        const hipError_t ec = hipStreamEndCapture(lead->bat_cap, &graph);
+        if (rc != GF2_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        GF2_HIP(ec);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        GF2_HIP(ei);
+        lead->bat_graph = exec;
+        lead->bat_key = key;
+    }
+    const int ph = prof_begin(lead, GF2_KC_DYSON);
+    GF2_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(lead->bat_graph), lead->stream));
+    double work = 0.0;
+    for (int s = 0; s < nsys; ++s)
+        if (req[s].mode >= 0) work += 8.0 * std::pow((double)req[s].c->n, 3) * req[s].d->niw;
+    prof_end(lead, ph, work);
+    GF2_HIP(hipMemcpyAsync(out_h, out_d, (size_t)nsys * 8 * 8, hipMemcpyDeviceToHost, lead->stream));
+    GF2_HIP(hipStreamSynchronize(lead->stream));
+    for (int t = 0; t < nsys; ++t) {
+        const int s = sh.order[t];
+        if (req[s].mode < 0) continue;
+        GF2_TRY(dyson_post(tab_h[t], out_h + (size_t)t * 8, &res[(size_t)2 * s]));
+    }
     return GF2_OK;
 }
 

@@ -83,6 +83,13 @@ struct gf2_ctx {
     gf2::DevBuf fock_part;
     gf2::DevBuf it_Sig_iw, it_G_iw, it_Sig1, it_mom, it_Sig_new, it_Pout, it_Pin, it_F, it_tmp;
     gf2::DevBuf it_hist;                  // Pulay history on the device: [2*depth][n][n]
+    // batched sweeps (gf2_iterate_batched, owned by the first context of the batch)
+    gf2::DevBuf bat_tab, bat_boff, bat_out;
+    void *bat_host = nullptr;             // pinned staging (hipHostMalloc)
+    size_t bat_host_bytes = 0;
+    void *bat_graph = nullptr;            // hipGraphExec_t of the Dyson round
+    hipStream_t bat_cap = nullptr;        // private stream the round is captured on
+    long long bat_key = 0;                // shape the graph was captured for
     gf2::DevBuf host_stage;               // unused placeholder for pinned staging
 };
 
@@ -136,6 +143,25 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
               double *mom_out, double *out);
 
 int fock_run(gf2_ctx *c, const double *P, double *F);
+
+// One round of Dyson solves for several systems (batched driver).  Job s:
+// mode (GF2_DYSON_*, or -1 to skip), mu, F, Sigma(i w), Sigma_1, and for
+// FULL/ENERGY the outputs G(i w), P and the tail moments.  res[s][0..1] as
+// the out[] of dyson_run.  All systems run on lead->stream.
+struct DysonReq {
+    gf2_ctx *c;
+    const gf2_dims *d;
+    int mode;
+    double mu;
+    const double *F;
+    const double2 *Sig;
+    const double *Sig1;
+    double2 *G_iw;
+    double *P;
+    double *mom;        // FULL/ENERGY: tail moments written here ([3][n][n])
+};
+int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<double> &res);
+void dyson_round_release(gf2_ctx *lead);
 
 // trigamma(x) for x > 0 (host)
 double trigamma(double x);

@@ -123,3 +123,29 @@ class Gf2:
     @property
     def mu(self):
         return self.state.mu if self.state is not None else math.nan
+
+
+class Gf2Batch:
+    """Several independent GF2 problems (e.g. a geometry sweep) on one GPU,
+    iterated together with gf2_iterate_batched.  ``systems``: Gf2 objects on
+    the same device (each keeps its own state)."""
+
+    def __init__(self, systems):
+        self.systems = list(systems)
+        if not self.systems:
+            raise ValueError("Gf2Batch needs at least one system")
+
+    def reset(self, mu0=None):
+        for g in self.systems:
+            g.reset(mu0=float(g.torch.diagonal(g.h).mean()) if mu0 is None else mu0)
+
+    def iterate(self, params):
+        for g in self.systems:
+            if g.state is None:
+                g.reset()
+        return L.gf2_iterate_batched([g.ctx for g in self.systems], [g.dims for g in self.systems],
+                                     params, [g.state for g in self.systems])
+
+    def close(self):
+        for g in self.systems:
+            g.close()
