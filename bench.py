@@ -46,6 +46,41 @@ def sigma_flops(n, ntau):
     return 8.0 * n ** 5 * ntau
 
 
+KERNEL_SOURCES = {"dyson": "dyson.hip", "sigma_gemm": "sigma.hip", "sigma_s23": "sigma.hip",
+                  "sigma_splitk": "sigma.hip", "t2i_expand": "fourier.hip", "i2t_fold": "fourier.hip",
+                  "fock": "fock.hip"}
+
+
+def source_hash(kernel_class):
+    import hashlib
+    f = os.path.join(ROOT, "paper_1405_3273_amd", "csrc", KERNEL_SOURCES[kernel_class])
+    with open(f, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel_class, workload, prec):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (profiles/pmc_traffic.md), or None when there is none for this
+    kernel class and workload or the kernel's source changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    i = text.find("```json")
+    if i < 0:
+        return None
+    j = text.find("```", i + 7)
+    try:
+        data = json.loads(text[i + 7:j])
+    except ValueError:
+        return None
+    for e in data.get("entries", []):
+        if (e.get("kernel_class") == kernel_class and e.get("workload") == workload
+                and e.get("prec") in (prec, None) and e.get("source_sha") == source_hash(kernel_class)):
+            return e.get("bytes_per_launch")
+    return None
+
+
 def cpu_baseline(sysm, counts, sample_tau=3, sample_freq=512):
     """The oracle, as it stands, on a bounded sample of one outer iteration:
     Eq. (Sigma) at `sample_tau` tau points and Eq. (GF) (+ density trace) at
@@ -92,6 +127,9 @@ def main():
     ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3",
                     help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device-to-device before the workload (a kernel of known\n"
+                         "traffic, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (the tau axis of "
@@ -103,6 +141,14 @@ def main():
     import synthetic
     from paper_1405_3273_amd import _lib as L
     from paper_1405_3273_amd.runtime import Gf2
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del a, b
 
     gen, desc = WORKLOADS[args.workload]
     t0 = time.perf_counter()
@@ -149,9 +195,13 @@ def main():
     unit = "GB/s" if bound == "hbm" else "TFLOP/s"
     scale = 1e9 if bound == "hbm" else 1e12
     roofline = {"bound": bound, "achieved": achieved / scale, "peak": PEAK[pk] / scale,
-                "unit": unit, "frac": achieved / PEAK[pk], "traffic": None,
+                "unit": unit, "frac": achieved / PEAK[pk],
+                "traffic": measured_traffic(dom, args.workload, args.prec),
                 "kernel": dom, "launches": cnt, "avg_launch_ms": avg_s * 1e3,
                 "work_per_launch": per_launch}
+    if bound == "mfma" and args.prec == "bf16x3":
+        roofline["note"] = ("BF16x3 issues 3 bf16 MFMA products per algorithmic FP32 MAC: "
+                            "frac is at most 1/3 against the bf16 peak")
     classes = {k: {"ms": v[0], "launches": v[1],
                    "rate": (v[2] / (v[0] / 1e3) / (1e9 if kind[k][0] == "hbm" else 1e12))
                    if v[0] > 0 else None,

@@ -322,39 +322,54 @@ __global__ __launch_bounds__(DY_TR * TC, 2) void k_dyson(DysonRef g) {
     }
 }
 
-// Tail moments of every job (one workgroup per job):
-// G1 = Sinv, G2 = Sinv H Sinv, G3 = Sinv H G2 (+ Sinv Sig1 Sinv in FULL/ENERGY),
-// H = F - mu S.  Products in the order of a plain row-by-column sum.
-__device__ void block_matmul(int n, const double *A, const double *B, double *C) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
-        C[e] = s;
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void k_moments(DysonRef g) {
-    const DysonJob a = job_of(g, blockIdx.x);
+// Tail moments of every job, in three stages (grid: x over elements, y over
+// jobs; one launch per stage):
+//   0: G1 = Sinv,  Y = Sinv (F - mu S)
+//   1: G2 = Y Sinv,  Z = Sinv Sig1 (FULL/ENERGY with Sig1)
+//   2: G3 = Y G2 (+ Z Sinv)
+// Each element is one plain row-by-column sum.
+__global__ __launch_bounds__(256) void k_moments(DysonRef g, int stage) {
+    const DysonJob a = job_of(g, blockIdx.y);
     if (a.mode < 0) return;
     const int n = a.n, ne = n * n;
-    double *H = a.scr, *Y = a.scr + ne, *Z = a.scr + 2 * ne;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int i = e / n, j = e - i * n;
+    double *Y = a.scr, *Z = a.scr + ne;
     double *G1 = a.mom, *G2 = a.mom + ne, *G3 = a.mom + 2 * ne;
-    const double b1 = 1.0, am = -a.mu;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        H[e] = am * a.S[e] + b1 * a.F[e];
+    const bool with_sig1 = a.mode != GF2_DYSON_TRACE && a.Sig1;
+    const double *Si = a.Sinv + (size_t)i * n;
+    if (stage == 0) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const size_t kj = (size_t)k * n + j;
+            s += Si[k] * fma(-a.mu, a.S[kj], a.F[kj]);
+        }
+        Y[e] = s;
         G1[e] = a.Sinv[e];
+    } else if (stage == 1) {
+        const double *Yi = Y + (size_t)i * n;
+        double s = 0.0, z = 0.0;
+        for (int k = 0; k < n; ++k) s += Yi[k] * a.Sinv[(size_t)k * n + j];
+        G2[e] = s;
+        if (with_sig1) {
+            for (int k = 0; k < n; ++k) z += Si[k] * a.Sig1[(size_t)k * n + j];
+            Z[e] = z;
+        }
+    } else {
+        const double *Yi = Y + (size_t)i * n, *Zi = Z + (size_t)i * n;
+        double s = 0.0, z = 0.0;
+        for (int k = 0; k < n; ++k) s += Yi[k] * G2[(size_t)k * n + j];
+        if (with_sig1)
+            for (int k = 0; k < n; ++k) z += Zi[k] * a.Sinv[(size_t)k * n + j];
+        G3[e] = s + z;
     }
-    __syncthreads();
-    block_matmul(n, a.Sinv, H, Y);   // Sinv H
-    block_matmul(n, Y, a.Sinv, G2);  // G2
-    block_matmul(n, Y, G2, G3);      // Sinv H G2
-    if (a.mode != GF2_DYSON_TRACE && a.Sig1) {
-        block_matmul(n, a.Sinv, a.Sig1, Z);
-        block_matmul(n, Z, a.Sinv, H);
-        for (int e = threadIdx.x; e < ne; e += blockDim.x) G3[e] = b1 * H[e] + b1 * G3[e];
-    }
+}
+
+static void launch_moments(const DysonRef &g, int njobs, int maxne, hipStream_t st) {
+    const dim3 grid((unsigned)((maxne + 255) / 256), (unsigned)njobs);
+    for (int stage = 0; stage < 3; ++stage)
+        hipLaunchKernelGGL(k_moments, grid, dim3(256), 0, st, g, stage);
 }
 
 // P = (4/beta) sum_b partP[b] + G1 - (beta/2) G2   (grid: x over elements, y over jobs)
@@ -513,7 +528,7 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     a.out = c->dys_out.as<double>();
     g.nsys = 0;
 
-    hipLaunchKernelGGL(k_moments, dim3(1), dim3(256), 0, c->stream, g);
+    launch_moments(g, 1, (int)ne, c->stream);
     const int ph = prof_begin(c, GF2_KC_DYSON);
     GF2_TRY(launch_dyson_class(dyson_class(n), dim3(nblocks), shm, c->stream, g));
     prof_end(c, ph, 8.0 * (double)n * n * n * niw);
@@ -574,8 +589,10 @@ static int enqueue_round(gf2_ctx *lead, hipStream_t st, const RoundShape &sh, in
     DysonRef all{};
     all.tab = tab;
     all.nsys = nsys;
-    hipLaunchKernelGGL(k_moments, dim3(nsys), dim3(256), 0, st, all);
     const int ncls = (int)sh.cls_ra.size();
+    int maxne = 1;
+    for (int k = 0; k < ncls; ++k) maxne = std::max(maxne, 16 * sh.cls_ra[k] * 16 * sh.cls_ra[k]);
+    launch_moments(all, nsys, maxne, st);
     for (int k = 0; k < ncls; ++k) {
         DysonRef g{};
         g.tab = tab + sh.cls_begin[k];
@@ -584,8 +601,6 @@ static int enqueue_round(gf2_ctx *lead, hipStream_t st, const RoundShape &sh, in
         const int nblk = sh.boff[sh.cls_begin[k + 1] + k];
         GF2_TRY(launch_dyson_class(sh.cls_ra[k], dim3(nblk), sh.shm[k], st, g));
     }
-    int maxne = 1;
-    for (int k = 0; k < ncls; ++k) maxne = std::max(maxne, 16 * sh.cls_ra[k] * 16 * sh.cls_ra[k]);
     hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((maxne + 255) / 256), (unsigned)nsys), dim3(256),
                        0, st, all);
     hipLaunchKernelGGL(k_finish, dim3(nsys), dim3(256), 0, st, all);
