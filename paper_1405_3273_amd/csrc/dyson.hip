@@ -13,8 +13,10 @@
 // k (a 16-lane shuffle argmax), scales it and eliminates column k from every
 // other row.  Rows are never moved; the pivot order r_k is kept, and the
 // physical element (i, j) ends up as G[rinv(i)][r(j)] (rinv = inverse of r).
-// Two barriers per step: after column k and the pivot are published, and
-// after the pivot row is published.
+// One workgroup barrier per step, after column k and the pivot are
+// published.  The pivot row is published through LDS per column: every wave
+// holds all rows of its own columns, so its lanes read only entries written
+// by lanes of the same wave and need no second barrier.
 //
 #include "gf2_internal.h"
 
@@ -225,7 +227,12 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 perm[k] = r;
                 rinv[r] = k;
             }
-            __syncthreads();
+            // Each lane reads only the sh_row entries of its own columns, written
+            // by the row-r owner of its 16-lane group in the same wave: LDS order
+            // within a wave suffices, no workgroup barrier.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (active) {
                 double2 crow[CB];
 #pragma unroll
