@@ -313,6 +313,219 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
         for (int e = tid; e < n * n; e += nthr) a.partP[(size_t)lb * n * n + e] = shP[e];
 }
 
+// ---------------------------------------------------------------------------
+// Small matrices (n <= 48): one wave per frequency, DW waves per workgroup,
+// no workgroup barrier.  Lane = 16 c + t (c < 4 column groups, t < 16): rows
+// t + 16a (a < RA), columns c + 4b (b < CB).  The 16 owners of a column are one
+// DPP row, so the pivot argmax stays a 16-lane reduction; pivot column,
+// factors and pivot row go through wave-private LDS (LDS operations of one
+// wave execute in order).  The owners of column k also form the factors
+// f_i = M[i][k]/p (f_r = 1 - 1/p), so the other lanes only read them.
+// Partial sums: one slot per wave (slot = workgroup * DW + wave).
+constexpr int DW = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int RA, int CB>
+__device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, const int nwg) {
+    constexpr int NR = 16 * RA, NC = 4 * CB;
+    const int n = a.n;
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int tr = lane & 15, tc = lane >> 4;
+    const int slot = lb * DW + wv, nslot = nwg * DW;
+
+    __shared__ double2 s_col[DW][NR];
+    __shared__ double2 s_f[DW][NR];
+    __shared__ double2 s_row[DW][NC];
+    __shared__ int s_r[DW];
+    __shared__ int s_perm[DW][NC > NR ? NC : NR], s_rinv[DW][NC > NR ? NC : NR];
+    extern __shared__ double shP[];   // [DW][n*n] when FULL/ENERGY and p_in_lds
+    double2 *col = s_col[wv], *fv = s_f[wv], *row = s_row[wv];
+    int *perm = s_perm[wv], *rinv = s_rinv[wv];
+
+    const bool full = a.mode != GF2_DYSON_TRACE;
+    double *Pacc = a.p_in_lds ? shP + (size_t)wv * n * n : (a.partP + (size_t)slot * n * n);
+    if (full)
+        for (int e = lane; e < n * n; e += 64) Pacc[e] = 0.0;
+    int sing = 0;
+    double acc_tr = 0.0, acc_e = 0.0;
+    double mr[RA][CB], mi[RA][CB];
+
+    for (int nn = slot; nn < a.niw; nn += nslot) {
+        const double w = M_PI * (double)(2 * nn + 1) / a.beta;
+        const double2 *Sig = a.Sig ? a.Sig + (size_t)nn * n * n : nullptr;
+#pragma unroll
+        for (int ia = 0; ia < RA; ++ia)
+#pragma unroll
+            for (int jb = 0; jb < CB; ++jb) {
+                const int i = tr + 16 * ia, j = tc + 4 * jb;
+                mr[ia][jb] = 0.0;
+                mi[ia][jb] = 0.0;
+                if (i < n && j < n) {
+                    const int e = i * n + j;
+                    const double sv = a.S[e];
+                    double re = a.mu * sv - a.F[e], im = w * sv;
+                    if (Sig) {
+                        const double2 sg = Sig[e];
+                        re -= sg.x;
+                        im -= sg.y;
+                    }
+                    mr[ia][jb] = re;
+                    mi[ia][jb] = im;
+                }
+            }
+        unsigned pivmask = 0;
+        wave_sync();   // previous frequency done with perm / rinv
+        for (int k = 0; k < n; ++k) {
+            const int kc = k & 3;
+            const int cb = __builtin_amdgcn_readfirstlane(k >> 2);
+            if (tc == kc) {
+                double best = -1.0;
+                int bi = n;
+#pragma unroll
+                for (int jb = 0; jb < CB; ++jb) {
+                    if (jb == cb) {   // scalar branch
+#pragma unroll
+                        for (int ia = 0; ia < RA; ++ia) {
+                            const int i = tr + 16 * ia;
+                            col[i] = make_double2(mr[ia][jb], mi[ia][jb]);
+                            const double mag = fabs(mr[ia][jb]) + fabs(mi[ia][jb]);
+                            const bool cand = !((pivmask >> ia) & 1u) && mag > best;
+                            best = cand ? mag : best;
+                            bi = cand ? i : bi;
+                        }
+                    }
+                }
+                argmax_step<8>(best, bi);
+                argmax_step<4>(best, bi);
+                argmax_step<2>(best, bi);
+                argmax_step<1>(best, bi);
+                const int r = (best > 0.0 && bi < n) ? bi : -1;
+                wave_sync();
+                const double2 ip = cinv(col[r < 0 ? k : r]);
+#pragma unroll
+                for (int jb = 0; jb < CB; ++jb) {
+                    if (jb == cb) {   // scalar branch
+#pragma unroll
+                        for (int ia = 0; ia < RA; ++ia) {
+                            const int i = tr + 16 * ia;
+                            const double vx = mr[ia][jb], vy = mi[ia][jb];
+                            double fx = vx * ip.x - vy * ip.y;
+                            double fy = vx * ip.y + vy * ip.x;
+                            if (i == r) {
+                                fx = 1.0 - ip.x;
+                                fy = -ip.y;
+                            }
+                            fv[i] = make_double2(fx, fy);
+                            mr[ia][jb] = 0.0;   // preset column k
+                            mi[ia][jb] = 0.0;
+                        }
+                    }
+                }
+                if (tr == 0) s_r[wv] = r;
+            }
+            wave_sync();
+            int r = s_r[wv];
+            if (r < 0) {
+                sing = 1;
+                r = k;
+            }
+            const int rr = r & 15;
+            const int ra = __builtin_amdgcn_readfirstlane(r >> 4);
+            if (tr == rr) {
+                pivmask |= 1u << ra;
+#pragma unroll
+                for (int ia = 0; ia < RA; ++ia) {
+                    if (ia == ra) {   // scalar branch
+#pragma unroll
+                        for (int jb = 0; jb < CB; ++jb) {
+                            if (jb == cb && tc == kc) mr[ia][jb] = 1.0;
+                            row[tc + 4 * jb] = make_double2(mr[ia][jb], mi[ia][jb]);
+                        }
+                    }
+                }
+            }
+            if (lane == 0) {
+                perm[k] = r;
+                rinv[r] = k;
+            }
+            wave_sync();
+            double2 fr[RA];
+#pragma unroll
+            for (int ia = 0; ia < RA; ++ia) fr[ia] = fv[tr + 16 * ia];
+#pragma unroll
+            for (int jb = 0; jb < CB; ++jb) {
+                const double2 c = row[tc + 4 * jb];
+#pragma unroll
+                for (int ia = 0; ia < RA; ++ia) {
+                    mr[ia][jb] = fma(-fr[ia].x, c.x, mr[ia][jb]);
+                    mr[ia][jb] = fma(fr[ia].y, c.y, mr[ia][jb]);
+                    mi[ia][jb] = fma(-fr[ia].x, c.y, mi[ia][jb]);
+                    mi[ia][jb] = fma(-fr[ia].y, c.x, mi[ia][jb]);
+                }
+            }
+            wave_sync();   // this step's reads before the next step's writes
+        }
+        // physical (i, j) holds G[rinv(i)][perm(j)]
+        const double iw2 = 1.0 / (w * w);
+#pragma unroll
+        for (int ia = 0; ia < RA; ++ia)
+#pragma unroll
+            for (int jb = 0; jb < CB; ++jb) {
+                const int i = tr + 16 * ia, j = tc + 4 * jb;
+                if (!(i < n && j < n)) continue;
+                const int ga = rinv[i], gb = perm[j];
+                const size_t e = (size_t)ga * n + gb;
+                if (!full) {
+                    acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
+                } else {
+                    Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
+                    if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
+                    if (a.mode == GF2_DYSON_ENERGY && Sig) {
+                        const double2 sg = Sig[(size_t)gb * n + ga];
+                        acc_e += mr[ia][jb] * sg.x - mi[ia][jb] * sg.y;
+                    }
+                }
+            }
+    }
+    // wave reductions (fixed order)
+    double v0 = acc_tr, v1 = acc_e;
+    for (int off = 32; off > 0; off >>= 1) {
+        v0 += __shfl_down(v0, off);
+        v1 += __shfl_down(v1, off);
+    }
+    if (lane == 0) {
+        double *ps = a.parts + (size_t)slot * 4;
+        ps[0] = v0;
+        ps[1] = v1;
+        ps[2] = (double)sing;
+        ps[3] = 0.0;
+    }
+    if (full && a.p_in_lds) {
+        wave_sync();
+        for (int e = lane; e < n * n; e += 64) a.partP[(size_t)slot * n * n + e] = Pacc[e];
+    }
+}
+
+template <int RA, int CB, bool GRP>
+__global__ __launch_bounds__(64 * DW) void k_dyson_w(DysonRef g) {
+    if constexpr (GRP) {
+        int sys = 0;
+        while (sys + 1 < g.nsys && g.boff[sys + 1] <= (int)blockIdx.x) ++sys;
+        sys = __builtin_amdgcn_readfirstlane(sys);
+        const DysonJob a = g.tab[sys];
+        if (a.mode < 0) return;
+        dyson_wave<RA, CB>(a, (int)blockIdx.x - g.boff[sys], a.nbl / DW);
+    } else {
+        dyson_wave<RA, CB>(g.one, (int)blockIdx.x, (int)gridDim.x);
+    }
+}
+
 // GRP: the jobs come from the table (batched launch), else the job is the
 // kernel argument itself (its fields stay reloadable kernel-argument reads).
 template <int RA, int CB, int TC, bool GRP>
@@ -444,15 +657,31 @@ static int launch_dyson(dim3 grid, size_t shm, hipStream_t s, const DysonRef &g,
     return GF2_OK;
 }
 
-// Size class of the register-resident inverse (rows per thread)
+template <int RA, int CB>
+static int launch_dyson_w(dim3 grid, size_t shm, hipStream_t s, const DysonRef &g,
+                          bool attr_only = false) {
+    const void *fn = (g.nsys > 0) ? reinterpret_cast<const void *>(&k_dyson_w<RA, CB, true>)
+                                  : reinterpret_cast<const void *>(&k_dyson_w<RA, CB, false>);
+    if (shm > 0) GF2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    if (attr_only) return GF2_OK;
+    if (g.nsys > 0)
+        hipLaunchKernelGGL((k_dyson_w<RA, CB, true>), grid, dim3(64 * DW), shm, s, g);
+    else
+        hipLaunchKernelGGL((k_dyson_w<RA, CB, false>), grid, dim3(64 * DW), shm, s, g);
+    return GF2_OK;
+}
+
+// Size class of the register-resident inverse (rows per thread); classes 1-3
+// (n <= 48) use the wave-per-frequency kernel.
 static int dyson_class(int n) { return (n + DY_TR - 1) / DY_TR; }
+static bool dyson_wave_class(int ra) { return ra <= 3; }
 
 static int launch_dyson_class(int ra, dim3 grid, size_t shm, hipStream_t s, const DysonRef &g,
                               bool attr_only = false) {
     switch (ra) {
-        case 1: return launch_dyson<1, 1, 16>(grid, shm, s, g, attr_only);
-        case 2: return launch_dyson<2, 2, 16>(grid, shm, s, g, attr_only);
-        case 3: return launch_dyson<3, 3, 16>(grid, shm, s, g, attr_only);
+        case 1: return launch_dyson_w<1, 4>(grid, shm, s, g, attr_only);
+        case 2: return launch_dyson_w<2, 8>(grid, shm, s, g, attr_only);
+        case 3: return launch_dyson_w<3, 12>(grid, shm, s, g, attr_only);
         case 4: return launch_dyson<4, 4, 16>(grid, shm, s, g, attr_only);
         case 5: return launch_dyson<5, 5, 16>(grid, shm, s, g, attr_only);
         case 6: return launch_dyson<6, 6, 16>(grid, shm, s, g, attr_only);
@@ -463,15 +692,28 @@ static int launch_dyson_class(int ra, dim3 grid, size_t shm, hipStream_t s, cons
     }
 }
 
-// Workgroups per job: two resident per CU give each a partner to overlap
-// barriers with; LDS P accumulation only while it keeps that.
-static int dyson_blocks(gf2_ctx *c, int niw) {
+// Partial-sum slots of a job and its workgroups.  Workgroup kernel: one slot
+// per workgroup, two resident per CU (each has a partner to overlap barriers
+// with).  Wave kernel: one slot per wave, DW waves per workgroup, about eight
+// waves per CU.
+static int dyson_slots(gf2_ctx *c, int n, int niw) {
     int dev_cus = 256;
     (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (dyson_wave_class(dyson_class(n))) {
+        const int waves = std::max(1, std::min(niw, 8 * dev_cus));
+        return (waves + DW - 1) / DW * DW;
+    }
     return std::max(1, std::min(niw, 2 * dev_cus));
 }
-static bool dyson_p_in_lds(int n, int mode) {
-    return mode != GF2_DYSON_TRACE && (size_t)n * n * 8 <= 32 * 1024;
+static int dyson_workgroups(int n, int slots) {
+    return dyson_wave_class(dyson_class(n)) ? slots / DW : slots;
+}
+// P accumulation in LDS (FULL/ENERGY) while it keeps two workgroups per CU
+static size_t dyson_shm(int n, int mode) {
+    if (mode == GF2_DYSON_TRACE) return 0;
+    const size_t ne8 = (size_t)n * n * 8;
+    const size_t need = dyson_wave_class(dyson_class(n)) ? DW * ne8 : ne8;
+    return need <= 32 * 1024 ? need : 0;
 }
 
 // Host part of a job's result: h = out[0..4] of k_finish
@@ -509,9 +751,9 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     const size_t ne = (size_t)n * n;
     if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
     const bool full = mode != GF2_DYSON_TRACE;
-    const int nblocks = dyson_blocks(c, niw);
-    const bool p_in_lds = dyson_p_in_lds(n, mode);
-    const size_t shm = p_in_lds ? ne * 8 : 0;
+    const int nblocks = dyson_slots(c, n, niw);
+    const size_t shm = dyson_shm(n, mode);
+    const bool p_in_lds = shm > 0;
 
     GF2_TRY(c->dys_X.ensure(6 * ne * 8));
     GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
@@ -537,7 +779,7 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
 
     launch_moments(g, 1, (int)ne, c->stream);
     const int ph = prof_begin(c, GF2_KC_DYSON);
-    GF2_TRY(launch_dyson_class(dyson_class(n), dim3(nblocks), shm, c->stream, g));
+    GF2_TRY(launch_dyson_class(dyson_class(n), dim3(dyson_workgroups(n, nblocks)), shm, c->stream, g));
     prof_end(c, ph, 8.0 * (double)n * n * n * niw);
     GF2_HIP(hipGetLastError());
     if (full)
@@ -624,7 +866,7 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
     for (int s = 0; s < nsys; ++s) {
         if (req[s].c->n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
         ra[s] = dyson_class(req[s].c->n);
-        nbl[s] = dyson_blocks(req[s].c, req[s].d->niw);
+        nbl[s] = dyson_slots(req[s].c, req[s].c->n, req[s].d->niw);
     }
     long long key = nsys;
     for (int r = 1; r <= 10; ++r) {
@@ -647,9 +889,8 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
         for (int t = sh.cls_begin[k]; t < sh.cls_begin[k + 1]; ++t) {
             const int s = sh.order[t];
             sh.boff.push_back(acc);
-            acc += nbl[s];
-            const size_t ne = (size_t)req[s].c->n * req[s].c->n;
-            if (dyson_p_in_lds(req[s].c->n, GF2_DYSON_FULL)) shm = std::max(shm, ne * 8);
+            acc += dyson_workgroups(req[s].c->n, nbl[s]);
+            shm = std::max(shm, dyson_shm(req[s].c->n, GF2_DYSON_FULL));
             key = key * 1000003LL + (long long)req[s].c->n * 7919 + nbl[s];
         }
         sh.boff.push_back(acc);
@@ -692,7 +933,7 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
         a.n = n;
         a.niw = q.d->niw;
         a.mode = q.mode;
-        a.p_in_lds = dyson_p_in_lds(n, q.mode) ? 1 : 0;
+        a.p_in_lds = dyson_shm(n, q.mode) > 0 ? 1 : 0;
         a.nbl = nbl[s];
         a.beta = q.d->beta;
         a.mu = q.mu;

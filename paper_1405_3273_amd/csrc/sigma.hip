@@ -26,6 +26,21 @@
 
 namespace gf2 {
 
+// ---------------------------------------------------------------------------
+// XCD-aware block order.  Consecutive workgroup ids are handed to the 8 XCDs
+// in turn; the remap gives every XCD a contiguous range of logical blocks, so
+// blocks that share operands (neighbouring logical ids) share one L2.  The
+// grid is launched with 8 * ceil(total / 8) blocks; ids past `total` exit.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_logical(int total) {
+    const int per = (total + NXCD - 1) / NXCD;
+    return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+}
+static unsigned xcd_grid(long long total) {
+    return (unsigned)(((total + NXCD - 1) / NXCD) * NXCD);
+}
+
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -52,7 +67,27 @@ struct GemmArgs {
     // goes to C[z*sC + m*ldc + q*pld + k] (hi) and the same index + plane (lo)
     int pn, pld;
     long long plane;
+    // XCD-ordered 1-D launch when gx > 0: logical block (x, y, z), x fastest,
+    // so the row blocks that share a B column block run on one XCD
+    int gx, gy, gz;
 };
+
+// Block coordinates of a GEMM launch (false: an id past the XCD-padded grid)
+__device__ __forceinline__ bool gemm_block(const GemmArgs &g, int &bx, int &by, int &bz) {
+    if (g.gx <= 0) {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        bz = blockIdx.z;
+        return true;
+    }
+    const int total = g.gx * g.gy * g.gz;
+    const int L = xcd_logical(total);
+    if (L >= total) return false;
+    bx = L % g.gx;
+    by = (L / g.gx) % g.gy;
+    bz = L / (g.gx * g.gy);
+    return true;
+}
 
 constexpr int NTHREADS = 256;
 constexpr int BM = 128;  // 4 waves x 2 row tiles x 16
@@ -91,9 +126,10 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int z = blockIdx.z;
-    const long long mb = (long long)blockIdx.x * BM;
-    const int nb = blockIdx.y * BN;
+    int bx, by, z;
+    if (!gemm_block(g, bx, by, z)) return;
+    const long long mb = (long long)bx * BM;
+    const int nb = by * BN;
 
     const in_t *A = static_cast<const in_t *>(g.A) + (long long)z * g.sA;
     const in_t *B = static_cast<const in_t *>(g.B) + (long long)z * g.sB;
@@ -263,9 +299,10 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int z = blockIdx.z;
-    const long long mb = (long long)blockIdx.x * BM;
-    const int nb = blockIdx.y * BN;
+    int bx, by, z;
+    if (!gemm_block(g, bx, by, z)) return;
+    const long long mb = (long long)bx * BM;
+    const int nb = by * BN;
 
     const float *A = static_cast<const float *>(g.A) + (long long)z * g.sA;
     const float *B = static_cast<const float *>(g.B) + (long long)z * g.sB;
@@ -460,20 +497,6 @@ int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a) {
     launch_nt<MODE_F64, true, true, 0>(nt, grid, c->stream, g);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
-}
-
-// ---------------------------------------------------------------------------
-// XCD-aware block order.  Consecutive workgroup ids are handed to the 8 XCDs
-// in turn; the remap gives every XCD a contiguous range of logical blocks, so
-// blocks that share operands (neighbouring logical ids) share one L2.  The
-// grid is launched with 8 * ceil(total / 8) blocks; ids past `total` exit.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_logical(int total) {
-    const int per = (total + NXCD - 1) / NXCD;
-    return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
-}
-static unsigned xcd_grid(long long total) {
-    return (unsigned)(((total + NXCD - 1) / NXCD) * NXCD);
 }
 
 // k / n for k < 2^22 (K = n^3 <= 160^3): the float quotient is within 1/8 of
@@ -765,25 +788,29 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(S23Args a
         T *xbase = X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
 #pragma unroll 1
         for (int lt = 0; lt < KT; ++lt) {
-            acc_t acc2 = acc_t{0, 0, 0, 0};
+            // two accumulation chains (even / odd k tiles), added at the end
+            acc_t acc2 = acc_t{0, 0, 0, 0}, acc2b = acc_t{0, 0, 0, 0};
             const T *grow = Gop + (16 * lt + c) * SL + 4 * g;
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) {
+                acc_t &ac = (kt & 1) ? acc2b : acc2;
                 if constexpr (MODE == MODE_F64) {
                     const double2 g0 = *reinterpret_cast<const double2 *>(grow + 16 * kt);
                     const double2 g1 = *reinterpret_cast<const double2 *>(grow + 16 * kt + 2);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.x, acc1[kt][0], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], acc2, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.x, acc1[kt][0], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], ac, 0, 0, 0);
                 } else {
                     const float4 gv = *reinterpret_cast<const float4 *>(grow + 16 * kt);
-                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, acc1[kt][0], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], acc2, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], acc2, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, acc1[kt][0], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], ac, 0, 0, 0);
+                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], ac, 0, 0, 0);
                 }
             }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc2[e] += acc2b[e];
             if (p < N) {
                 if constexpr (MODE == MODE_F64) {
 #pragma unroll
@@ -1591,7 +1618,11 @@ int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, doub
             g.alpha = 1.0;
             g.vecA = 0;
             int nt;
-            const dim3 grid = gemm_grid(g, n, nt);
+            dim3 grid = gemm_grid(g, n, nt);
+            g.gx = (int)grid.x;
+            g.gy = (int)grid.y;
+            g.gz = (int)grid.z;
+            grid = dim3(xcd_grid((long long)g.gx * g.gy * g.gz));
             const int ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
             if (mode == MODE_F64) {
                 launch_nt<MODE_F64, false, true, 16>(nt, grid, c->stream, g);
