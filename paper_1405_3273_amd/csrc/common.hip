@@ -320,6 +320,7 @@ int gf2_ctx_destroy(gf2_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     prof_release(c);
+    sigma_release(c);
     dyson_round_release(c);
     gf2::DevBuf *bufs[] = {&c->S,        &c->Sinv,      &c->h,       &c->v,        &c->v_32,
                            &c->W2_64,    &c->W2_32,     &c->W2_b3,   &c->sig_T1,   &c->sig_X,    &c->sig_Gp,  &c->sig_Gq,
@@ -328,7 +329,7 @@ int gf2_ctx_destroy(gf2_ctx *c) {
                            &c->dys_out,  &c->fock_part, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
                            &c->it_mom,   &c->it_Sig_new, &c->it_Pout, &c->it_Pin,  &c->it_F,
                            &c->it_tmp,   &c->it_hist,   &c->host_stage, &c->bat_tab,  &c->bat_boff,
-                           &c->bat_out};
+                           &c->bat_out,  &c->sig_tab};
     for (auto *b : bufs) b->release();
     delete c;
     return GF2_OK;

@@ -493,22 +493,25 @@ namespace gf2 {
 
 // Steps 3 and the Sigma part of an outer iteration: Sigma(tau) from G(tau),
 // damping, Sigma(i w) and Sigma_1.  Iteration 0 (Hartree-Fock) has no Sigma.
-static int iter_sigma(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
-                      const double2 **Sig, const double **Sig1, double *t_sig, double *t_four) {
+static int iter_sigma_prep(gf2_ctx *c, const gf2_dims *d, const gf2_state *st, const double2 **Sig,
+                           const double **Sig1, bool *need) {
     const size_t ne = (size_t)c->n * c->n;
     const size_t nt = (size_t)d->ntau * ne;
     GF2_TRY(c->it_Sig1.ensure(ne * 8));
     *Sig = nullptr;
     *Sig1 = nullptr;
-    if (st->iteration == 0) return GF2_OK;
+    *need = st->iteration != 0;
+    if (!*need) return GF2_OK;
     GF2_TRY(c->it_Sig_new.ensure(nt * 8));
     GF2_TRY(c->it_Sig_iw.ensure((size_t)d->niw * ne * 16));
+    return GF2_OK;
+}
+
+// new Sigma(tau) in it_Sig_new: check, damp, keep, transform to iw
+static int iter_sigma_post(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
+                           const double2 **Sig, const double **Sig1, double *t_four) {
+    const size_t nt = (size_t)d->ntau * c->n * c->n;
     double *Snew = c->it_Sig_new.as<double>();
-    GF2_HIP(hipStreamSynchronize(c->stream));
-    const double ts = now_ms();
-    GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, Snew));
-    GF2_HIP(hipStreamSynchronize(c->stream));
-    *t_sig += now_ms() - ts;
     int bad = 0;
     GF2_TRY(any_nonfinite(c, nt, Snew, &bad));
     if (bad) return fail(GF2_ENONFINITE, "gf2_iterate: non-finite self-energy");
@@ -522,6 +525,19 @@ static int iter_sigma(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_st
     *Sig = c->it_Sig_iw.as<double2>();
     *Sig1 = c->it_Sig1.as<double>();
     return GF2_OK;
+}
+
+static int iter_sigma(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_state *st,
+                      const double2 **Sig, const double **Sig1, double *t_sig, double *t_four) {
+    bool need;
+    GF2_TRY(iter_sigma_prep(c, d, st, Sig, Sig1, &need));
+    if (!need) return GF2_OK;
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    const double ts = now_ms();
+    GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, c->it_Sig_new.as<double>()));
+    GF2_HIP(hipStreamSynchronize(c->stream));
+    *t_sig += now_ms() - ts;
+    return iter_sigma_post(c, d, p, st, Sig, Sig1, t_four);
 }
 
 // End of an outer iteration after the inner loop: F(P_out), E_1b, G(tau),
@@ -640,8 +656,32 @@ extern "C" int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dim
     double t_sig = 0.0, t_four = 0.0;
     std::vector<const double2 *> Sig(nsys);
     std::vector<const double *> Sig1(nsys);
-    for (int s = 0; s < nsys; ++s)
-        GF2_TRY(iter_sigma(ctxs[s], &dims[s], p, &states[s], &Sig[s], &Sig1[s], &t_sig, &t_four));
+    {
+        // Sigma(tau) of every system that needs one: one captured graph
+        std::vector<gf2_ctx *> cs;
+        std::vector<int> nt;
+        std::vector<const double *> G;
+        std::vector<double *> So;
+        for (int s = 0; s < nsys; ++s) {
+            bool need;
+            GF2_TRY(iter_sigma_prep(ctxs[s], &dims[s], &states[s], &Sig[s], &Sig1[s], &need));
+            if (!need) continue;
+            cs.push_back(ctxs[s]);
+            nt.push_back(dims[s].ntau);
+            G.push_back(states[s].G_tau);
+            So.push_back(ctxs[s]->it_Sig_new.as<double>());
+        }
+        if (!cs.empty()) {
+            GF2_HIP(hipStreamSynchronize(lead->stream));
+            const double ts = now_ms();
+            GF2_TRY(sigma_run_batched(lead, cs, nt, p->prec, G, So));
+            GF2_HIP(hipStreamSynchronize(lead->stream));
+            t_sig += now_ms() - ts;
+            for (int s = 0; s < nsys; ++s)
+                if (states[s].iteration != 0)
+                    GF2_TRY(iter_sigma_post(ctxs[s], &dims[s], p, &states[s], &Sig[s], &Sig1[s], &t_four));
+        }
+    }
 
     const double ti = now_ms();
     std::vector<InnerLoop> il(nsys);

@@ -89,6 +89,9 @@ struct gf2_ctx {
     size_t bat_host_bytes = 0;
     void *bat_graph = nullptr;            // hipGraphExec_t of the Dyson round
     hipStream_t bat_cap = nullptr;        // private stream the round is captured on
+    gf2::DevBuf sig_tab;                  // argument tables of the batched Sigma launches
+    void *sig_graph = nullptr;            // hipGraphExec_t of the batched Sigma
+    long long sig_key = 0;
     long long bat_key = 0;                // shape the graph was captured for
     gf2::DevBuf host_stage;               // unused placeholder for pinned staging
 };
@@ -129,6 +132,11 @@ int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a);
 // ---- stages ---------------------------------------------------------------------
 int sigma_build_layouts(gf2_ctx *c, bool want_f32);
 int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau);
+// Sigma(tau) of many systems (one lead context runs the captured graph)
+int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std::vector<int> &ntau,
+                      int prec, const std::vector<const double *> &G,
+                      const std::vector<double *> &Sig);
+void sigma_release(gf2_ctx *c);
 
 int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2 *Sig_iw,
                    double *Sig1);

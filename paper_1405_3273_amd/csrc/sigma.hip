@@ -22,7 +22,13 @@
 #include "gf2_internal.h"
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
 
 namespace gf2 {
 
@@ -72,17 +78,52 @@ struct GemmArgs {
     int gx, gy, gz;
 };
 
-// Block coordinates of a GEMM launch (false: an id past the XCD-padded grid)
-__device__ __forceinline__ bool gemm_block(const GemmArgs &g, int &bx, int &by, int &bz) {
-    if (g.gx <= 0) {
+// Kernel argument of the Sigma kernels: one problem (nsys == 0, the args
+// themselves) or a table of problems of many systems run by one launch.  The
+// launch is a 1-D grid in XCD order over `total` logical blocks; system s owns
+// logical blocks [boff[s], boff[s+1]) and gets its own block index from 0.
+template <class A> struct KRef {
+    A one;
+    const A *tab;
+    const int *boff;
+    int nsys;
+    int total;
+};
+
+// a, L: the problem of this workgroup and its local logical block (false:
+// an id past the padded grid).  Single problems give `total_one` blocks.
+template <class A>
+__device__ __forceinline__ bool kresolve(const KRef<A> &r, int total_one, A &a, int &L) {
+    if (r.nsys == 0) {
+        L = xcd_logical(total_one);
+        if (L >= total_one) return false;
+        a = r.one;
+        return true;
+    }
+    const int Lg = xcd_logical(r.total);
+    if (Lg >= r.total) return false;
+    int sys = 0;
+    while (sys + 1 < r.nsys && r.boff[sys + 1] <= Lg) ++sys;
+    sys = __builtin_amdgcn_readfirstlane(sys);
+    a = r.tab[sys];
+    L = Lg - r.boff[sys];
+    return true;
+}
+
+// Block coordinates of a GEMM workgroup (false: an id past the XCD-padded grid).
+// gx > 0: logical (x, y, z), x fastest, from the XCD-ordered 1-D grid (single
+// problem or a table); gx == 0: the 3-D grid as launched (single problem only).
+__device__ __forceinline__ bool gemm_block(const KRef<GemmArgs> &r, GemmArgs &g, int &bx, int &by,
+                                           int &bz) {
+    if (r.nsys == 0 && r.one.gx <= 0) {
+        g = r.one;
         bx = blockIdx.x;
         by = blockIdx.y;
         bz = blockIdx.z;
         return true;
     }
-    const int total = g.gx * g.gy * g.gz;
-    const int L = xcd_logical(total);
-    if (L >= total) return false;
+    int L;
+    if (!kresolve(r, r.one.gx * r.one.gy * r.one.gz, g, L)) return false;
     bx = L % g.gx;
     by = (L / g.gx) % g.gy;
     bz = L / (g.gx * g.gy);
@@ -109,7 +150,7 @@ template <class T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 // OUT64: FP64 output (FP32 accumulators flushed into FP64 every 512 K);
 // BK_: K chunk (0 = the mode's default; the k-major form needs 16).
 template <int MODE, bool AK, int NT, bool OUT64, int BK_>
-__global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
+__global__ __launch_bounds__(NTHREADS) void gemm_fp(KRef<GemmArgs> r) {
     using in_t = typename ModeT<MODE>::in_t;
     using acc_t = typename ModeT<MODE>::acc_t;
     constexpr int BK = BK_ ? BK_ : ModeT<MODE>::BK;
@@ -126,8 +167,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    GemmArgs g;
     int bx, by, z;
-    if (!gemm_block(g, bx, by, z)) return;
+    if (!gemm_block(r, g, bx, by, z)) return;
     const long long mb = (long long)bx * BM;
     const int nb = by * BN;
 
@@ -286,7 +328,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(GemmArgs g) {
 // BF16x3 kernel: FP32 operands split into hi/lo BF16 in LDS, tiles As[m][k], Bs[n][k]
 // PLANES: output split into bf16 hi/lo planes (see GemmArgs), else FP32.
 template <bool AK, int NT, bool PLANES>
-__global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
+__global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
     constexpr int BK = 32;
     constexpr int BN = 16 * NT;
     constexpr int SK = BK + 8;       // padded k stride (bf16 elements)
@@ -299,8 +341,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    GemmArgs g;
     int bx, by, z;
-    if (!gemm_block(g, bx, by, z)) return;
+    if (!gemm_block(r, g, bx, by, z)) return;
     const long long mb = (long long)bx * BM;
     const int nb = by * BN;
 
@@ -455,13 +498,13 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(GemmArgs g) {
 
 // OUT64: FP64 output for gemm_fp; for gemm_bf3 it selects the hi/lo plane output.
 template <int MODE, bool AK, bool OUT64, int BK_>
-static void launch_nt(int nt, dim3 grid, hipStream_t s, const GemmArgs &g) {
+static void launch_nt(int nt, dim3 grid, hipStream_t s, const KRef<GemmArgs> &r) {
 #define GF2_NT_CASE(T)                                                                      \
     case T:                                                                                 \
         if constexpr (MODE == MODE_BF3)                                                     \
-            hipLaunchKernelGGL((gemm_bf3<AK, T, OUT64>), grid, dim3(NTHREADS), 0, s, g);    \
+            hipLaunchKernelGGL((gemm_bf3<AK, T, OUT64>), grid, dim3(NTHREADS), 0, s, r);    \
         else                                                                                \
-            hipLaunchKernelGGL((gemm_fp<MODE, AK, T, OUT64, BK_>), grid, dim3(NTHREADS), 0, s, g); \
+            hipLaunchKernelGGL((gemm_fp<MODE, AK, T, OUT64, BK_>), grid, dim3(NTHREADS), 0, s, r); \
         break;
     switch (nt) {
         GF2_NT_CASE(1) GF2_NT_CASE(2) GF2_NT_CASE(3) GF2_NT_CASE(4)
@@ -494,7 +537,9 @@ int gemm_f64_kmajor(gf2_ctx *c, const GemmArgsF64 &a) {
     g.vecA = (a.lda % 2 == 0) ? 1 : 0;
     int nt;
     const dim3 grid = gemm_grid(g, 1, nt);
-    launch_nt<MODE_F64, true, true, 0>(nt, grid, c->stream, g);
+    KRef<GemmArgs> r{};
+    r.one = g;
+    launch_nt<MODE_F64, true, true, 0>(nt, grid, c->stream, r);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
@@ -636,17 +681,17 @@ template <int MODE, int KT> struct S23Threads {
 };
 
 template <int MODE, int KT, bool GLDS>
-__global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(S23Args a) {
+__global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23Args> ref) {
     using T = typename ModeT<MODE>::in_t;
     using acc_t = typename ModeT<MODE>::acc_t;
     constexpr int P16 = 16 * KT;
     constexpr int SL = P16 + S23Geom<MODE>::pad;
     extern __shared__ __attribute__((aligned(16))) unsigned char s23_smem[];
 
+    S23Args a;
+    int L;
+    if (!kresolve(ref, ref.one.nb * ref.one.n * KT, a, L)) return;
     const int N = a.n;
-    const int total = a.nb * N * KT;
-    const int L = xcd_logical(total);
-    if (L >= total) return;
     const int pt = L % KT;
     const int nn = (L / KT) % N;
     const int t = L / (KT * N);
@@ -855,7 +900,7 @@ constexpr int S4_THREADS = 64 * S4_WAVES;
 constexpr int S4_BM = 16 * S4_WAVES;
 
 template <int MODE, int NT>
-__global__ __launch_bounds__(S4_THREADS) void k_s4(S4Args a) {
+__global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
     using T = typename ModeT<MODE>::in_t;
     using acc_t = typename ModeT<MODE>::acc_t;
     constexpr bool F64 = (MODE == MODE_F64);
@@ -874,9 +919,9 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(S4Args a) {
     __shared__ __attribute__((aligned(16))) T As[BMR][SK];
     __shared__ __attribute__((aligned(16))) T Bs[BK][SB];
 
-    const int total = a.nrb * a.nsplit;
-    const int L = xcd_logical(total);
-    if (L >= total) return;
+    S4Args a;
+    int L;
+    if (!kresolve(ref, ref.one.nrb * ref.one.nsplit, a, L)) return;
     const int rb = L % a.nrb, z = L / a.nrb;
     const int N = a.n;
     const long long k0 = (long long)z * a.kz;
@@ -1111,16 +1156,16 @@ struct S23b3Args {
 };
 
 template <int KT>
-__global__ __launch_bounds__(512) void k_s23_bf3(S23b3Args a) {
+__global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     constexpr int KP = (KT + 1) / 2;          // 32-deep k steps of the second product
     constexpr int P16 = 16 * KT;
     constexpr int SLG = 32 * KP + 8;          // LDS row of Gq (bf16)
     extern __shared__ __attribute__((aligned(16))) unsigned char s23b_smem[];
 
+    S23b3Args a;
+    int L;
+    if (!kresolve(ref, ref.one.nb * ref.one.n * KT, a, L)) return;
     const int N = a.n;
-    const int total = a.nb * N * KT;
-    const int L = xcd_logical(total);
-    if (L >= total) return;
     const int pt = L % KT;
     const int nn = (L / KT) % N;
     const int t = L / (KT * N);
@@ -1277,7 +1322,7 @@ struct S4b3Args {
 };
 
 template <int NT>
-__global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(S4b3Args a) {
+__global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
     constexpr int BK = 64;
     constexpr int BN = 16 * NT;
     constexpr int SKB = BK + 8;                       // LDS row (bf16)
@@ -1287,9 +1332,9 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(S4b3Args a) {
     __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][SKB];
     __shared__ __attribute__((aligned(16))) unsigned short Bl[BN][SKB];
 
-    const int total = a.nrb * a.nsplit;
-    const int L = xcd_logical(total);
-    if (L >= total) return;
+    S4b3Args a;
+    int L;
+    if (!kresolve(ref, ref.one.nrb * ref.one.nsplit, a, L)) return;
     const int rb = L % a.nrb, z = L / a.nrb;
     const int N = a.n;
     const long long k0 = (long long)z * a.kz;
@@ -1406,114 +1451,144 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(S4b3Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// host-side launchers
+// host side: launches of one problem or of a table of problems
 
 template <int MODE, int KT>
-static int launch_s23_kt(gf2_ctx *c, const S23Args &a) {
+static constexpr size_t s23_lds_g() {
     using T = typename ModeT<MODE>::in_t;
-    constexpr int P16 = 16 * KT;
-    constexpr int SL = P16 + S23Geom<MODE>::pad;
-    const int S = (a.n + 3) / 4;
-    const size_t g_bytes = (size_t)P16 * SL * sizeof(T);
-    const size_t b_bytes = (size_t)4 * S * 16 * sizeof(T);
-    const bool glds = g_bytes + b_bytes <= (size_t)120 * 1024;
-    const size_t lds = (glds ? g_bytes : 0) + b_bytes;
-    // waves per workgroup: aim at ~16 resident waves per CU
+    return (size_t)16 * KT * (16 * KT + S23Geom<MODE>::pad) * sizeof(T);
+}
+static size_t s23_lds_b(int mode, int n) {
+    return (size_t)4 * ((n + 3) / 4) * 16 * (mode == MODE_F64 ? 8 : 4);
+}
+
+template <int MODE, int KT>
+static bool s23_glds() {
+    return s23_lds_g<MODE, KT>() + s23_lds_b(MODE, 16 * KT) <= (size_t)120 * 1024;
+}
+
+// default waves per S23 workgroup: ~16 resident waves per CU
+template <int MODE, int KT>
+static int s23_default_waves(int n) {
+    const size_t lds = (s23_glds<MODE, KT>() ? s23_lds_g<MODE, KT>() : 0) + s23_lds_b(MODE, n);
     const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int waves = std::min(S23Threads<MODE, KT>::value / 64, std::max(4, 16 / per_cu));
-    const dim3 grid(xcd_grid((long long)a.nb * a.n * KT));
-    if (glds) {
-        GF2_HIP(hipFuncSetAttribute((const void *)k_s23<MODE, KT, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((k_s23<MODE, KT, true>), grid, dim3(64 * waves), lds, c->stream, a);
-    } else {
-        GF2_HIP(hipFuncSetAttribute((const void *)k_s23<MODE, KT, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((k_s23<MODE, KT, false>), grid, dim3(64 * waves), lds, c->stream, a);
-    }
+    return std::min(S23Threads<MODE, KT>::value / 64, std::max(4, 16 / per_cu));
+}
+
+template <int MODE, int KT>
+static int launch_s23_kt(hipStream_t st, dim3 grid, int waves, size_t lds_b, const KRef<S23Args> &r,
+                         bool attr_only) {
+    const bool glds = s23_glds<MODE, KT>();
+    const size_t lds = (glds ? s23_lds_g<MODE, KT>() : 0) + lds_b;
+    waves = std::min(waves, S23Threads<MODE, KT>::value / 64);
+    const void *fn = glds ? (const void *)k_s23<MODE, KT, true> : (const void *)k_s23<MODE, KT, false>;
+    // the same limit (the largest any n of this KT needs) on every path
+    const size_t lds_max = (glds ? s23_lds_g<MODE, KT>() : 0) + s23_lds_b(MODE, 16 * KT);
+    GF2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+    if (attr_only) return GF2_OK;
+    if (glds) hipLaunchKernelGGL((k_s23<MODE, KT, true>), grid, dim3(64 * waves), lds, st, r);
+    else hipLaunchKernelGGL((k_s23<MODE, KT, false>), grid, dim3(64 * waves), lds, st, r);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
 template <int MODE>
-static int launch_s23(gf2_ctx *c, int kt, const S23Args &a) {
+static int launch_s23(hipStream_t st, int kt, dim3 grid, int waves, size_t lds_b,
+                      const KRef<S23Args> &r, bool attr_only = false) {
     switch (kt) {
-        case 1: return launch_s23_kt<MODE, 1>(c, a);
-        case 2: return launch_s23_kt<MODE, 2>(c, a);
-        case 3: return launch_s23_kt<MODE, 3>(c, a);
-        case 4: return launch_s23_kt<MODE, 4>(c, a);
-        case 5: return launch_s23_kt<MODE, 5>(c, a);
-        case 6: return launch_s23_kt<MODE, 6>(c, a);
-        case 7: return launch_s23_kt<MODE, 7>(c, a);
-        case 8: return launch_s23_kt<MODE, 8>(c, a);
-        case 9: return launch_s23_kt<MODE, 9>(c, a);
-        case 10: return launch_s23_kt<MODE, 10>(c, a);
+#define GF2_S23_CASE(K_) case K_: return launch_s23_kt<MODE, K_>(st, grid, waves, lds_b, r, attr_only);
+        GF2_S23_CASE(1) GF2_S23_CASE(2) GF2_S23_CASE(3) GF2_S23_CASE(4) GF2_S23_CASE(5)
+        GF2_S23_CASE(6) GF2_S23_CASE(7) GF2_S23_CASE(8) GF2_S23_CASE(9) GF2_S23_CASE(10)
+#undef GF2_S23_CASE
         default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
     }
 }
 
 template <int MODE>
-static int launch_s4(gf2_ctx *c, int nt, const S4Args &a) {
-    const dim3 grid(xcd_grid((long long)a.nrb * a.nsplit));
-#define GF2_S4_CASE(T_)                                                                    \
-    case T_:                                                                               \
-        hipLaunchKernelGGL((k_s4<MODE, T_>), grid, dim3(S4_THREADS), 0, c->stream, a);     \
-        break;
+static int default_waves(int kt, int n) {
+    switch (kt) {
+#define GF2_W_CASE(K_) case K_: return s23_default_waves<MODE, K_>(n);
+        GF2_W_CASE(1) GF2_W_CASE(2) GF2_W_CASE(3) GF2_W_CASE(4) GF2_W_CASE(5)
+        GF2_W_CASE(6) GF2_W_CASE(7) GF2_W_CASE(8) GF2_W_CASE(9) GF2_W_CASE(10)
+#undef GF2_W_CASE
+        default: return 4;
+    }
+}
+
+template <int MODE>
+static int max_waves(int kt) {
+    switch (kt) {
+#define GF2_M_CASE(K_) case K_: return S23Threads<MODE, K_>::value / 64;
+        GF2_M_CASE(1) GF2_M_CASE(2) GF2_M_CASE(3) GF2_M_CASE(4) GF2_M_CASE(5)
+        GF2_M_CASE(6) GF2_M_CASE(7) GF2_M_CASE(8) GF2_M_CASE(9) GF2_M_CASE(10)
+#undef GF2_M_CASE
+        default: return 4;
+    }
+}
+
+template <int MODE>
+static int launch_s4(hipStream_t st, int nt, dim3 grid, const KRef<S4Args> &r) {
     switch (nt) {
+#define GF2_S4_CASE(T_) case T_: hipLaunchKernelGGL((k_s4<MODE, T_>), grid, dim3(S4_THREADS), 0, st, r); break;
         GF2_S4_CASE(1) GF2_S4_CASE(2) GF2_S4_CASE(3) GF2_S4_CASE(4) GF2_S4_CASE(5)
         GF2_S4_CASE(6) GF2_S4_CASE(7) GF2_S4_CASE(8) GF2_S4_CASE(9) GF2_S4_CASE(10)
+#undef GF2_S4_CASE
         default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
     }
-#undef GF2_S4_CASE
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
 template <int KT>
-static int launch_s23_bf3_kt(gf2_ctx *c, const S23b3Args &a) {
+static size_t s23b3_lds(int n) {
     constexpr int KP = (KT + 1) / 2;
     constexpr int P16 = 16 * KT;
     constexpr int SLG = 32 * KP + 8;
-    const int SQ = 32 * ((a.n + 31) / 32) + 8;
-    const size_t lds = 2 * ((size_t)2 * P16 * SLG + (size_t)2 * 16 * SQ);
-    const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int waves = std::min(8, std::max(4, 16 / per_cu));
-    const dim3 grid(xcd_grid((long long)a.nb * a.n * KT));
+    const int SQ = 32 * ((n + 31) / 32) + 8;
+    return 2 * ((size_t)2 * P16 * SLG + (size_t)2 * 16 * SQ);
+}
+
+template <int KT>
+static int launch_s23_bf3_kt(hipStream_t st, dim3 grid, int waves, size_t lds,
+                             const KRef<S23b3Args> &r, bool attr_only) {
     GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_s23_bf3<KT>), grid, dim3(64 * waves), lds, c->stream, a);
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)s23b3_lds<KT>(16 * KT)));
+    if (attr_only) return GF2_OK;
+    hipLaunchKernelGGL((k_s23_bf3<KT>), grid, dim3(64 * std::min(waves, 8)), lds, st, r);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
-static int launch_s23_bf3(gf2_ctx *c, int kt, const S23b3Args &a) {
+static size_t s23_bf3_lds(int kt, int n) {
     switch (kt) {
-        case 1: return launch_s23_bf3_kt<1>(c, a);
-        case 2: return launch_s23_bf3_kt<2>(c, a);
-        case 3: return launch_s23_bf3_kt<3>(c, a);
-        case 4: return launch_s23_bf3_kt<4>(c, a);
-        case 5: return launch_s23_bf3_kt<5>(c, a);
-        case 6: return launch_s23_bf3_kt<6>(c, a);
-        case 7: return launch_s23_bf3_kt<7>(c, a);
-        case 8: return launch_s23_bf3_kt<8>(c, a);
-        case 9: return launch_s23_bf3_kt<9>(c, a);
-        case 10: return launch_s23_bf3_kt<10>(c, a);
+#define GF2_L_CASE(K_) case K_: return s23b3_lds<K_>(n);
+        GF2_L_CASE(1) GF2_L_CASE(2) GF2_L_CASE(3) GF2_L_CASE(4) GF2_L_CASE(5)
+        GF2_L_CASE(6) GF2_L_CASE(7) GF2_L_CASE(8) GF2_L_CASE(9) GF2_L_CASE(10)
+#undef GF2_L_CASE
+        default: return 0;
+    }
+}
+
+static int launch_s23_bf3(hipStream_t st, int kt, dim3 grid, int waves, size_t lds,
+                          const KRef<S23b3Args> &r, bool attr_only = false) {
+    switch (kt) {
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_>(st, grid, waves, lds, r, attr_only);
+        GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
+        GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9) GF2_B_CASE(10)
+#undef GF2_B_CASE
         default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
     }
 }
 
-static int launch_s4_bf3(gf2_ctx *c, int nt, const S4b3Args &a) {
-    const dim3 grid(xcd_grid((long long)a.nrb * a.nsplit));
-#define GF2_S4B_CASE(T_)                                                                    \
-    case T_:                                                                                \
-        hipLaunchKernelGGL((k_s4_bf3<T_>), grid, dim3(S4_THREADS), 0, c->stream, a);        \
-        break;
+static int launch_s4_bf3(hipStream_t st, int nt, dim3 grid, const KRef<S4b3Args> &r) {
     switch (nt) {
+#define GF2_S4B_CASE(T_) case T_: hipLaunchKernelGGL((k_s4_bf3<T_>), grid, dim3(S4_THREADS), 0, st, r); break;
         GF2_S4B_CASE(1) GF2_S4B_CASE(2) GF2_S4B_CASE(3) GF2_S4B_CASE(4) GF2_S4B_CASE(5)
         GF2_S4B_CASE(6) GF2_S4B_CASE(7) GF2_S4B_CASE(8) GF2_S4B_CASE(9) GF2_S4B_CASE(10)
+#undef GF2_S4B_CASE
         default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
     }
-#undef GF2_S4B_CASE
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
@@ -1533,182 +1608,605 @@ static int build_bf3_layouts(gf2_ctx *c) {
     return GF2_OK;
 }
 
-int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau) {
+// ---------------------------------------------------------------------------
+// One system's Sigma(tau): sizes, workspaces and launch shapes.  The tau batch
+// b and the waves per S23 workgroup change only which workgroup computes
+// which independent result, never the arithmetic of a result, so the
+// autotuner below may pick them freely.
+struct SigShape {
+    int b = 0;
+    int waves = 0;
+};
+
+struct SigPlan {
+    gf2_ctx *c = nullptr;
+    int mode = 0, n = 0, ntau = 0, M = 0;
+    const double *G = nullptr;
+    double *Sig = nullptr;
+    int KT = 0, SL = 0, lq = 0, KP = 0, SLG = 0, nsplit = 0, s1_bk = 16;
+    long long kz = 0;
+    size_t t1_plane = 0, gq_plane = 0;
+    SigShape sh;
+    const void *V = nullptr, *W2 = nullptr;
+};
+
+static int sigma_bmax(int n, int mode) {
+    const size_t esz = (mode == MODE_F64) ? 8 : 4;
+    const size_t N4 = (size_t)n * n * n * n;
+    const size_t budget = (size_t)16 << 30;   // T1 + X
+    return (int)std::min<size_t>(std::max<size_t>(1, budget / (2 * N4 * esz)), 64);
+}
+
+static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape sh,
+                     SigPlan &p) {
     const int n = c->n;
     if (n > 160) return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
-    const int ntau = d->ntau;
-    const int M = ntau - 1;
+    p = SigPlan();
+    p.c = c;
+    p.mode = prec;
+    p.n = n;
+    p.ntau = ntau;
+    p.M = ntau - 1;
+    p.G = G;
+    p.Sig = Sig;
     const long long N = n, N2 = N * N, N3 = N2 * N, N4 = N3 * N;
-    const int mode = prec;
-    if (mode == MODE_BF3 && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
-    const size_t esz = (mode == MODE_F64) ? 8 : 4;
-    if (mode != MODE_F64 && !c->have_f32_layouts) GF2_TRY(sigma_build_layouts(c, true));
-    const void *V = (mode == MODE_F64) ? c->v.ptr : c->v_32.ptr;
-    const void *W2 = (mode == MODE_F64) ? c->W2_64.ptr : c->W2_32.ptr;
-    const int KT = (n + 15) / 16;
-    const int SL = 16 * KT + ((mode == MODE_F64) ? S23Geom<MODE_F64>::pad : S23Geom<MODE_F32>::pad);
-
-    // tau batch: T1 and X hold b * N^4 elements each, capped at ~16 GB together
-    const size_t budget = (size_t)16 << 30;
-    const size_t bmax = std::max<size_t>(1, budget / (2 * (size_t)N4 * esz));
-    const int b = (int)std::min<size_t>(bmax, (size_t)std::min(ntau, 64));
-
-    // final contraction: K = N^3 split into slices of kz (a multiple of 512)
-    long long kz = 4096;
-    if (N3 < 8 * 4096) kz = std::max<long long>(512, ((N3 / 8) + 511) / 512 * 512);
-    const int nsplit = (int)((N3 + kz - 1) / kz);
-    const int NT = KT;
-
-    // BF16x3: T1 as hi/lo planes with rows padded to lq (zeroed once per call:
-    // the first transform never writes the padding)
-    const int lq = (n + 7) / 8 * 8;
-    const int KP = (KT + 1) / 2;
-    const int SLG = 32 * KP + 8;
-    const size_t t1_plane = (size_t)b * N2 * N * lq;
-    const size_t gq_plane = (size_t)b * 16 * KT * SLG;
-    if (mode == MODE_BF3) {
-        GF2_TRY(c->sig_T1.ensure(2 * t1_plane * 2));
-        GF2_TRY(c->sig_Gq.ensure(2 * gq_plane * 2));
-        GF2_TRY(fill_zero(c, c->sig_T1.ptr, 2 * t1_plane * 2));
+    const size_t esz = (p.mode == MODE_F64) ? 8 : 4;
+    if (p.mode != MODE_F64 && !c->have_f32_layouts) GF2_TRY(sigma_build_layouts(c, true));
+    if (p.mode == MODE_BF3 && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
+    p.V = (p.mode == MODE_F64) ? c->v.ptr : c->v_32.ptr;
+    p.W2 = (p.mode == MODE_F64) ? c->W2_64.ptr : c->W2_32.ptr;
+    p.KT = (n + 15) / 16;
+    p.SL = 16 * p.KT + ((p.mode == MODE_F64) ? S23Geom<MODE_F64>::pad : S23Geom<MODE_F32>::pad);
+    p.lq = (n + 7) / 8 * 8;
+    p.KP = (p.KT + 1) / 2;
+    p.SLG = 32 * p.KP + 8;
+    p.kz = 4096;
+    if (N3 < 8 * 4096) p.kz = std::max<long long>(512, ((N3 / 8) + 511) / 512 * 512);
+    p.nsplit = (int)((N3 + p.kz - 1) / p.kz);
+    p.s1_bk = (p.mode == MODE_F32 && n % 16 != 0 && n % 20 == 0) ? 20 : 16;
+    const int bmax = sigma_bmax(n, p.mode);
+    p.sh.b = std::max(1, std::min(sh.b > 0 ? sh.b : bmax, std::min(bmax, ntau)));
+    const int wmax = (p.mode == MODE_F64) ? max_waves<MODE_F64>(p.KT)
+                     : (p.mode == MODE_F32) ? max_waves<MODE_F32>(p.KT) : 8;
+    if (sh.waves > 0) {
+        p.sh.waves = std::min(sh.waves, wmax);
+    } else if (p.mode == MODE_BF3) {
+        const int per_cu = std::max<int>(1, (int)((160 * 1024) / s23_bf3_lds(p.KT, n)));
+        p.sh.waves = std::min(8, std::max(4, 16 / per_cu));
+    } else {
+        p.sh.waves = (p.mode == MODE_F64) ? default_waves<MODE_F64>(p.KT, n)
+                                          : default_waves<MODE_F32>(p.KT, n);
     }
-    GF2_TRY(c->sig_T1.ensure((size_t)b * N4 * esz));
-    GF2_TRY(c->sig_X.ensure((size_t)b * N4 * esz));
-    GF2_TRY(c->sig_G.ensure((size_t)b * N2 * esz));
-    GF2_TRY(c->sig_Gb.ensure((size_t)b * N2 * esz));
-    GF2_TRY(c->sig_Gp.ensure((size_t)b * 16 * KT * SL * esz));
-    GF2_TRY(c->sig_part.ensure((size_t)nsplit * b * N2 * 8));
+    const size_t b = (size_t)p.sh.b;
+    p.t1_plane = b * N2 * N * p.lq;
+    p.gq_plane = b * 16 * p.KT * p.SLG;
+    if (p.mode == MODE_BF3) {
+        GF2_TRY(c->sig_T1.ensure(2 * p.t1_plane * 2));
+        GF2_TRY(c->sig_Gq.ensure(2 * p.gq_plane * 2));
+    }
+    GF2_TRY(c->sig_T1.ensure(b * N4 * esz));
+    GF2_TRY(c->sig_X.ensure(b * N4 * esz));
+    GF2_TRY(c->sig_G.ensure(b * N2 * esz));
+    GF2_TRY(c->sig_Gb.ensure(b * N2 * esz));
+    GF2_TRY(c->sig_Gp.ensure(b * 16 * p.KT * p.SL * esz));
+    GF2_TRY(c->sig_part.ensure((size_t)p.nsplit * b * N2 * 8));
+    return GF2_OK;
+}
 
-    for (int k0 = 0; k0 < ntau; k0 += b) {
-        const int nb = std::min(b, ntau - k0);
-        {
-            const size_t tot = (size_t)nb * N2;
-            const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
-            const size_t totp = (size_t)nb * 16 * KT * SL;
-            const unsigned blocksp = (unsigned)std::min<size_t>((totp + 255) / 256, 4096);
-            if (mode == MODE_F64) {
-                hipLaunchKernelGGL(k_stage_g<double>, dim3(blocks), dim3(256), 0, c->stream, n, M,
-                                   k0, nb, G_tau, c->sig_G.as<double>(), c->sig_Gb.as<double>());
-                hipLaunchKernelGGL((k_stage_gp<double, true>), dim3(blocksp), dim3(256), 0,
-                                   c->stream, n, KT, SL, M, k0, nb, G_tau, c->sig_Gp.as<double>());
-            } else {
-                hipLaunchKernelGGL(k_stage_g<float>, dim3(blocks), dim3(256), 0, c->stream, n, M,
-                                   k0, nb, G_tau, c->sig_G.as<float>(), c->sig_Gb.as<float>());
-                if (mode == MODE_F32) {
-                    hipLaunchKernelGGL((k_stage_gp<float, false>), dim3(blocksp), dim3(256), 0,
-                                       c->stream, n, KT, SL, M, k0, nb, G_tau, c->sig_Gp.as<float>());
-                } else {
-                    const size_t totq = (size_t)nb * 16 * KT * SLG;
-                    const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
-                    hipLaunchKernelGGL(k_stage_gq, dim3(blocksq), dim3(256), 0, c->stream, n, KP,
-                                       SLG, 16 * KT, k0, nb, gq_plane, G_tau,
-                                       c->sig_Gq.as<unsigned short>());
+// staging of G(tau), G(-tau) for tau points k0 .. k0 + nb - 1
+static int plan_stage(const SigPlan &p, hipStream_t st, int k0, int nb) {
+    gf2_ctx *c = p.c;
+    const int n = p.n;
+    const size_t N2 = (size_t)n * n;
+    const size_t tot = (size_t)nb * N2;
+    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
+    const size_t totp = (size_t)nb * 16 * p.KT * p.SL;
+    const unsigned blocksp = (unsigned)std::min<size_t>((totp + 255) / 256, 4096);
+    if (p.mode == MODE_F64) {
+        hipLaunchKernelGGL(k_stage_g<double>, dim3(blocks), dim3(256), 0, st, n, p.M, k0, nb, p.G,
+                           c->sig_G.as<double>(), c->sig_Gb.as<double>());
+        hipLaunchKernelGGL((k_stage_gp<double, true>), dim3(blocksp), dim3(256), 0, st, n, p.KT, p.SL,
+                           p.M, k0, nb, p.G, c->sig_Gp.as<double>());
+    } else {
+        hipLaunchKernelGGL(k_stage_g<float>, dim3(blocks), dim3(256), 0, st, n, p.M, k0, nb, p.G,
+                           c->sig_G.as<float>(), c->sig_Gb.as<float>());
+        if (p.mode == MODE_F32) {
+            hipLaunchKernelGGL((k_stage_gp<float, false>), dim3(blocksp), dim3(256), 0, st, n, p.KT,
+                               p.SL, p.M, k0, nb, p.G, c->sig_Gp.as<float>());
+        } else {
+            const size_t totq = (size_t)nb * 16 * p.KT * p.SLG;
+            const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_stage_gq, dim3(blocksq), dim3(256), 0, st, n, p.KP, p.SLG, 16 * p.KT,
+                               k0, nb, p.gq_plane, p.G, c->sig_Gq.as<unsigned short>());
+        }
+    }
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+static int plan_reduce(const SigPlan &p, hipStream_t st, int k0, int nb) {
+    const size_t tot = (size_t)nb * p.n * p.n;
+    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_reduce_split, dim3(blocks), dim3(256), 0, st, p.n, nb, p.nsplit,
+                       p.c->sig_part.as<double>(), p.Sig, k0);
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+// arguments of the three contraction stages for a batch of nb tau points
+static GemmArgs plan_s1(const SigPlan &p, int nb, int &nt) {
+    const long long N = p.n, N2 = N * N, N3 = N2 * N;
+    const long long R = (long long)nb * N;
+    GemmArgs g{};
+    g.A = p.c->sig_G.ptr; g.lda = N; g.sA = 0;
+    g.B = p.V; g.ldb = N2; g.sB = N3;
+    g.C = p.c->sig_T1.ptr; g.ldc = N2; g.sC = R * N2;
+    g.M = (int)R; g.N = (int)N2; g.K = p.n; g.kz = p.n; g.split = 0;
+    g.alpha = 1.0;
+    g.vecA = 0;
+    if (p.mode == MODE_BF3) {
+        g.vecA = (p.n % 4 == 0) ? 1 : 0;
+        g.pn = p.n;
+        g.pld = p.lq;
+        g.ldc = N * p.lq;
+        g.sC = R * N * p.lq;
+        g.plane = (long long)p.t1_plane;
+    }
+    const dim3 grid = gemm_grid(g, p.n, nt);
+    g.gx = (int)grid.x;
+    g.gy = (int)grid.y;
+    g.gz = (int)grid.z;
+    return g;
+}
+
+static S23Args plan_s23(const SigPlan &p, int nb) {
+    return S23Args{p.c->sig_T1.ptr, p.c->sig_Gp.ptr, p.c->sig_Gb.ptr, p.c->sig_X.ptr, p.n, nb};
+}
+
+static S23b3Args plan_s23b3(const SigPlan &p, int nb) {
+    S23b3Args a{};
+    a.T1 = p.c->sig_T1.as<unsigned short>();
+    a.t1_plane = (long long)p.t1_plane;
+    a.lq = p.lq;
+    a.Gq = p.c->sig_Gq.as<unsigned short>();
+    a.gq_plane = (long long)p.gq_plane;
+    a.Gb = p.c->sig_Gb.as<float>();
+    a.X = p.c->sig_X.as<float>();
+    a.n = p.n;
+    a.nb = nb;
+    return a;
+}
+
+static S4Args plan_s4(const SigPlan &p, int nb) {
+    const long long N = p.n, N3 = N * N * N;
+    const long long R = (long long)nb * N;
+    S4Args a{};
+    a.X = p.c->sig_X.ptr;
+    a.W = p.W2;
+    a.part = p.c->sig_part.as<double>();
+    a.K = N3;
+    a.kz = p.kz;
+    a.n = p.n;
+    a.R = (int)R;
+    a.nrb = (int)((R + S4_BM - 1) / S4_BM);
+    a.nsplit = p.nsplit;
+    a.vec = (p.mode == MODE_F64) ? (p.n % 2 == 0) : (p.n % 4 == 0);
+    return a;
+}
+
+static S4b3Args plan_s4b3(const SigPlan &p, int nb) {
+    const S4Args a = plan_s4(p, nb);
+    const long long nkc = (a.K + 63) / 64;
+    S4b3Args b{};
+    b.X = p.c->sig_X.as<float>();
+    b.W2b = p.c->W2_b3.as<unsigned short>();
+    b.plane = nkc * 16 * p.KT * 64;
+    b.part = a.part;
+    b.K = a.K;
+    b.kz = a.kz;
+    b.n = a.n;
+    b.R = a.R;
+    b.nrb = a.nrb;
+    b.nsplit = a.nsplit;
+    b.vec = (p.n % 4 == 0);
+    return b;
+}
+
+static int launch_s1(int mode, int bk, int nt, dim3 grid, hipStream_t st, const KRef<GemmArgs> &r) {
+    if (mode == MODE_F64) launch_nt<MODE_F64, false, true, 16>(nt, grid, st, r);
+    else if (mode == MODE_BF3) launch_nt<MODE_BF3, false, true, 0>(nt, grid, st, r);
+    else if (bk == 20) launch_nt<MODE_F32, false, false, 20>(nt, grid, st, r);
+    else launch_nt<MODE_F32, false, false, 16>(nt, grid, st, r);
+    GF2_HIP(hipGetLastError());
+    return GF2_OK;
+}
+
+// One tau batch of one system, arguments by value (no table).
+static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool prof) {
+    gf2_ctx *c = p.c;
+    const double fl = 2.0 * std::pow((double)p.n, 5) * nb;
+    GF2_TRY(plan_stage(p, st, k0, nb));
+    {
+        int nt;
+        KRef<GemmArgs> r{};
+        r.one = plan_s1(p, nb, nt);
+        const dim3 grid(xcd_grid((long long)r.one.gx * r.one.gy * r.one.gz));
+        const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_GEMM) : -1;
+        GF2_TRY(launch_s1(p.mode, p.s1_bk, nt, grid, st, r));
+        if (prof) prof_end(c, ph, fl);
+    }
+    {
+        const dim3 grid(xcd_grid((long long)nb * p.n * p.KT));
+        const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_S23) : -1;
+        if (p.mode == MODE_BF3) {
+            KRef<S23b3Args> r{};
+            r.one = plan_s23b3(p, nb);
+            GF2_TRY(launch_s23_bf3(st, p.KT, grid, p.sh.waves, s23_bf3_lds(p.KT, p.n), r));
+        } else {
+            KRef<S23Args> r{};
+            r.one = plan_s23(p, nb);
+            if (p.mode == MODE_F64)
+                GF2_TRY(launch_s23<MODE_F64>(st, p.KT, grid, p.sh.waves, s23_lds_b(p.mode, p.n), r));
+            else
+                GF2_TRY(launch_s23<MODE_F32>(st, p.KT, grid, p.sh.waves, s23_lds_b(p.mode, p.n), r));
+        }
+        if (prof) prof_end(c, ph, 2.0 * fl);
+    }
+    {
+        const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_SPLITK) : -1;
+        if (p.mode == MODE_BF3) {
+            KRef<S4b3Args> r{};
+            r.one = plan_s4b3(p, nb);
+            const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit));
+            GF2_TRY(launch_s4_bf3(st, p.KT, grid, r));
+        } else {
+            KRef<S4Args> r{};
+            r.one = plan_s4(p, nb);
+            const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit));
+            if (p.mode == MODE_F64) GF2_TRY(launch_s4<MODE_F64>(st, p.KT, grid, r));
+            else GF2_TRY(launch_s4<MODE_F32>(st, p.KT, grid, r));
+        }
+        if (prof) prof_end(c, ph, fl);
+    }
+    return plan_reduce(p, st, k0, nb);
+}
+
+static int plan_run(SigPlan &p, bool prof) {
+    if (p.mode == MODE_BF3)   // the first transform never writes the padding of the T1 rows
+        GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, 2 * p.t1_plane * 2));
+    for (int k0 = 0; k0 < p.ntau; k0 += p.sh.b)
+        GF2_TRY(plan_run_batch(p, p.c->stream, k0, std::min(p.sh.b, p.ntau - k0), prof));
+    return GF2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: on the first Sigma(tau) of an (n, ntau, precision) class, time
+// each candidate shape on the first tau batch of the real input and keep the
+// fastest per tau point (process-wide cache).  GF2_SIGMA_TUNE=0 in the
+// environment skips tuning (default shape).
+struct TuneKey {
+    int n, ntau, mode;
+    bool operator<(const TuneKey &o) const {
+        return n != o.n ? n < o.n : ntau != o.ntau ? ntau < o.ntau : mode < o.mode;
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, SigShape> g_tune;
+
+static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape &out) {
+    // GF2_SIGMA_SHAPE="b,waves" forces a shape (read on every call; for tests
+    // of the invariance and for sweeps)
+    if (const char *fs = std::getenv("GF2_SIGMA_SHAPE")) {
+        int b = 0, w = 0;
+        if (std::sscanf(fs, "%d,%d", &b, &w) == 2 && b > 0 && w > 0) {
+            out = SigShape{b, w};
+            return GF2_OK;
+        }
+    }
+    const TuneKey key{c->n, ntau, prec};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            out = it->second;
+            return GF2_OK;
+        }
+    }
+    const char *env = std::getenv("GF2_SIGMA_TUNE");
+    SigShape best{};
+    if (!(env && env[0] == '0')) {
+        const int bmax = std::min(sigma_bmax(c->n, prec), ntau);
+        std::vector<int> bs;
+        for (int b : {bmax, (bmax + 1) / 2, (bmax + 3) / 4})
+            if (b >= 1 && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
+        std::vector<int> ws = (prec == MODE_BF3) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+        hipEvent_t e0, e1;
+        GF2_HIP(hipEventCreate(&e0));
+        GF2_HIP(hipEventCreate(&e1));
+        double best_t = 1e300;
+        int rc = GF2_OK;
+        for (int b : bs) {
+            for (int w : ws) {
+                SigPlan p;
+                rc = plan_init(c, ntau, prec, G, Sig, SigShape{b, w}, p);
+                if (rc != GF2_OK) break;
+                if (p.sh.waves != w) continue;   // not a distinct shape for this class
+                if (prec == MODE_BF3) rc = fill_zero(c, c->sig_T1.ptr, 2 * p.t1_plane * 2);
+                if (rc != GF2_OK) break;
+                const int nb = std::min(b, ntau);
+                (void)hipEventRecord(e0, c->stream);
+                rc = plan_run_batch(p, c->stream, 0, nb, false);
+                (void)hipEventRecord(e1, c->stream);
+                if (rc != GF2_OK) break;
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(GF2_EHIP, "autotuner: event"); break; }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                const double per_tau = ms / nb;
+                if (per_tau < best_t) {
+                    best_t = per_tau;
+                    best = SigShape{b, p.sh.waves};
                 }
             }
-            GF2_HIP(hipGetLastError());
+            if (rc != GF2_OK) break;
         }
-        const long long R = (long long)nb * N;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        GF2_TRY(rc);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    out = best;
+    return GF2_OK;
+}
 
-        // S1: T1[i][(t,n)][(q,k)] = sum_m Gs[(t,n)][m] v[i][m][(q,k)], batched over i
-        {
-            GemmArgs g{};
-            g.A = c->sig_G.ptr; g.lda = N; g.sA = 0;
-            g.B = V; g.ldb = N2; g.sB = N3;
-            g.C = c->sig_T1.ptr; g.ldc = N2; g.sC = R * N2;
-            g.M = (int)R; g.N = (int)N2; g.K = n; g.kz = n; g.split = 0;
-            g.alpha = 1.0;
-            g.vecA = 0;
+int sigma_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau) {
+    SigShape sh;
+    GF2_TRY(tuned_shape(c, d->ntau, prec, G_tau, Sigma_tau, sh));
+    SigPlan p;
+    GF2_TRY(plan_init(c, d->ntau, prec, G_tau, Sigma_tau, sh, p));
+    return plan_run(p, true);
+}
+
+// ---------------------------------------------------------------------------
+// Many systems: every tau batch of every system in shared launches (one per
+// kernel class and stage), captured once per batch shape into a HIP graph on
+// the lead context's capture stream and replayed on its stream.  The argument
+// tables of all launches are uploaded once with the capture.
+
+struct GroupLaunch {
+    int stage;      // 1 = S1, 2 = S23, 4 = S4
+    int cls_a, cls_b, cls_c;   // S1: bk, nt, -; S23: KT, waves, -; S4: NT
+    size_t tab_off, boff_off;  // byte offsets into the table buffer
+    int nsys, total;
+    size_t lds;
+};
+
+template <class A>
+static void push_table(std::vector<unsigned char> &buf, const std::vector<A> &tab,
+                       const std::vector<int> &boff, GroupLaunch &gl) {
+    auto align = [&](size_t a) { while (buf.size() % a) buf.push_back(0); };
+    align(16);
+    gl.tab_off = buf.size();
+    const unsigned char *t = reinterpret_cast<const unsigned char *>(tab.data());
+    buf.insert(buf.end(), t, t + tab.size() * sizeof(A));
+    align(16);
+    gl.boff_off = buf.size();
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(boff.data());
+    buf.insert(buf.end(), b, b + boff.size() * sizeof(int));
+}
+
+int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std::vector<int> &ntau,
+                      int prec, const std::vector<const double *> &G,
+                      const std::vector<double *> &Sig) {
+    const int ns = (int)cs.size();
+    std::vector<SigPlan> plans(ns);
+    for (int s = 0; s < ns; ++s) {
+        SigShape sh;
+        GF2_TRY(tuned_shape(cs[s], ntau[s], prec, G[s], Sig[s], sh));
+        GF2_TRY(plan_init(cs[s], ntau[s], prec, G[s], Sig[s], sh, plans[s]));
+    }
+    if (prec == MODE_BF3)
+        for (auto &p : plans) GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, 2 * p.t1_plane * 2));
+    // shape key: everything the captured launches depend on
+    long long key = 1469598103934665603LL ^ prec;
+    auto mix = [&](long long v) { key = (key ^ v) * 1099511628211LL; };
+    for (auto &p : plans) {
+        mix(p.n); mix(p.ntau); mix(p.sh.b); mix(p.sh.waves);
+        mix((long long)(uintptr_t)p.G); mix((long long)(uintptr_t)p.Sig);
+        mix((long long)(uintptr_t)p.c->sig_T1.ptr); mix((long long)(uintptr_t)p.c->sig_X.ptr);
+        mix((long long)(uintptr_t)p.c->sig_part.ptr); mix((long long)(uintptr_t)p.c->sig_Gp.ptr);
+        mix((long long)(uintptr_t)p.c->sig_Gq.ptr); mix((long long)(uintptr_t)p.V);
+        mix((long long)(uintptr_t)p.W2); mix((long long)(uintptr_t)p.c->W2_b3.ptr);
+    }
+    if (lead->sig_graph && lead->sig_key == key) {
+        GF2_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(lead->sig_graph), lead->stream));
+        return GF2_OK;
+    }
+    if (lead->sig_graph) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(lead->sig_graph));
+        lead->sig_graph = nullptr;
+        lead->sig_key = 0;
+    }
+    // rounds: round r = tau batch r of every system that has one
+    int rounds = 0;
+    for (auto &p : plans) rounds = std::max(rounds, (p.ntau + p.sh.b - 1) / p.sh.b);
+    std::vector<unsigned char> buf;
+    std::vector<std::vector<GroupLaunch>> per_round(rounds);
+    for (int r = 0; r < rounds; ++r) {
+        std::vector<int> act;
+        for (int s = 0; s < ns; ++s)
+            if (r * plans[s].sh.b < plans[s].ntau) act.push_back(s);
+        auto nb_of = [&](int s) { return std::min(plans[s].sh.b, plans[s].ntau - r * plans[s].sh.b); };
+        // S1 classes (bk, nt)
+        std::map<std::pair<int, int>, std::vector<int>> c1;
+        for (int s : act) {
             int nt;
-            dim3 grid = gemm_grid(g, n, nt);
-            g.gx = (int)grid.x;
-            g.gy = (int)grid.y;
-            g.gz = (int)grid.z;
-            grid = dim3(xcd_grid((long long)g.gx * g.gy * g.gz));
-            const int ph = prof_begin(c, GF2_KC_SIGMA_GEMM);
-            if (mode == MODE_F64) {
-                launch_nt<MODE_F64, false, true, 16>(nt, grid, c->stream, g);
-            } else if (mode == MODE_BF3) {
-                g.vecA = (n % 4 == 0) ? 1 : 0;
-                g.pn = n;
-                g.pld = lq;
-                g.ldc = N * lq;
-                g.sC = R * N * lq;
-                g.plane = (long long)t1_plane;
-                launch_nt<MODE_BF3, false, true, 0>(nt, grid, c->stream, g);
-            } else if (n % 16 != 0 && n % 20 == 0) {
-                launch_nt<MODE_F32, false, false, 20>(nt, grid, c->stream, g);
-            } else {
-                launch_nt<MODE_F32, false, false, 16>(nt, grid, c->stream, g);
-            }
-            GF2_HIP(hipGetLastError());
-            prof_end(c, ph, 2.0 * (double)N4 * (double)N * nb);
+            (void)plan_s1(plans[s], nb_of(s), nt);
+            c1[{plans[s].s1_bk, nt}].push_back(s);
         }
-        // S2 + S3 fused
-        {
-            const int ph = prof_begin(c, GF2_KC_SIGMA_S23);
-            if (mode == MODE_BF3) {
-                S23b3Args a{};
-                a.T1 = c->sig_T1.as<unsigned short>();
-                a.t1_plane = (long long)t1_plane;
-                a.lq = lq;
-                a.Gq = c->sig_Gq.as<unsigned short>();
-                a.gq_plane = (long long)gq_plane;
-                a.Gb = c->sig_Gb.as<float>();
-                a.X = c->sig_X.as<float>();
-                a.n = n;
-                a.nb = nb;
-                GF2_TRY(launch_s23_bf3(c, KT, a));
-            } else {
-                S23Args a{c->sig_T1.ptr, c->sig_Gp.ptr, c->sig_Gb.ptr, c->sig_X.ptr, n, nb};
-                if (mode == MODE_F64) GF2_TRY(launch_s23<MODE_F64>(c, KT, a));
-                else GF2_TRY(launch_s23<MODE_F32>(c, KT, a));
+        for (auto &kv : c1) {
+            std::vector<GemmArgs> tab;
+            std::vector<int> boff{0};
+            for (int s : kv.second) {
+                int nt;
+                tab.push_back(plan_s1(plans[s], nb_of(s), nt));
+                boff.push_back(boff.back() + tab.back().gx * tab.back().gy * tab.back().gz);
             }
-            prof_end(c, ph, 4.0 * (double)N4 * (double)N * nb);
+            GroupLaunch gl{1, kv.first.first, kv.first.second, 0, 0, 0, (int)tab.size(), boff.back(), 0};
+            push_table(buf, tab, boff, gl);
+            per_round[r].push_back(gl);
         }
-        // S4: split-K final contraction
-        {
-            S4Args a{};
-            a.X = c->sig_X.ptr;
-            a.W = W2;
-            a.part = c->sig_part.as<double>();
-            a.K = N3;
-            a.kz = kz;
-            a.n = n;
-            a.R = (int)R;
-            a.nrb = (int)((R + S4_BM - 1) / S4_BM);
-            a.nsplit = nsplit;
-            a.vec = (mode == MODE_F64) ? (n % 2 == 0) : (n % 4 == 0);
-            const int ph = prof_begin(c, GF2_KC_SIGMA_SPLITK);
-            if (mode == MODE_F64) {
-                GF2_TRY(launch_s4<MODE_F64>(c, NT, a));
-            } else if (mode == MODE_F32) {
-                GF2_TRY(launch_s4<MODE_F32>(c, NT, a));
+        // S23 classes (KT, waves)
+        std::map<std::pair<int, int>, std::vector<int>> c2;
+        for (int s : act) c2[{plans[s].KT, plans[s].sh.waves}].push_back(s);
+        for (auto &kv : c2) {
+            std::vector<int> boff{0};
+            size_t lds = 0;
+            GroupLaunch gl{2, kv.first.first, kv.first.second, 0, 0, 0, (int)kv.second.size(), 0, 0};
+            if (prec == MODE_BF3) {
+                std::vector<S23b3Args> tab;
+                for (int s : kv.second) {
+                    tab.push_back(plan_s23b3(plans[s], nb_of(s)));
+                    boff.push_back(boff.back() + nb_of(s) * plans[s].n * plans[s].KT);
+                    lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n));
+                }
+                push_table(buf, tab, boff, gl);
             } else {
-                const long long nkc = (N3 + 63) / 64;
-                S4b3Args ab{};
-                ab.X = c->sig_X.as<float>();
-                ab.W2b = c->W2_b3.as<unsigned short>();
-                ab.plane = nkc * 16 * NT * 64;
-                ab.part = a.part;
-                ab.K = a.K;
-                ab.kz = a.kz;
-                ab.n = n;
-                ab.R = a.R;
-                ab.nrb = a.nrb;
-                ab.nsplit = a.nsplit;
-                ab.vec = (n % 4 == 0);
-                GF2_TRY(launch_s4_bf3(c, NT, ab));
+                std::vector<S23Args> tab;
+                for (int s : kv.second) {
+                    tab.push_back(plan_s23(plans[s], nb_of(s)));
+                    boff.push_back(boff.back() + nb_of(s) * plans[s].n * plans[s].KT);
+                    lds = std::max(lds, s23_lds_b(prec, plans[s].n));
+                }
+                push_table(buf, tab, boff, gl);
             }
-            prof_end(c, ph, 2.0 * (double)N4 * (double)N * nb);
+            gl.total = boff.back();
+            gl.lds = lds;
+            per_round[r].push_back(gl);
         }
-        {
-            const size_t tot = (size_t)nb * N2;
-            const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_reduce_split, dim3(blocks), dim3(256), 0, c->stream, n, nb,
-                               nsplit, c->sig_part.as<double>(), Sigma_tau, k0);
-            GF2_HIP(hipGetLastError());
+        // S4 classes (NT)
+        std::map<int, std::vector<int>> c4;
+        for (int s : act) c4[plans[s].KT].push_back(s);
+        for (auto &kv : c4) {
+            std::vector<int> boff{0};
+            GroupLaunch gl{4, kv.first, 0, 0, 0, 0, (int)kv.second.size(), 0, 0};
+            if (prec == MODE_BF3) {
+                std::vector<S4b3Args> tab;
+                for (int s : kv.second) {
+                    tab.push_back(plan_s4b3(plans[s], nb_of(s)));
+                    boff.push_back(boff.back() + tab.back().nrb * tab.back().nsplit);
+                }
+                push_table(buf, tab, boff, gl);
+            } else {
+                std::vector<S4Args> tab;
+                for (int s : kv.second) {
+                    tab.push_back(plan_s4(plans[s], nb_of(s)));
+                    boff.push_back(boff.back() + tab.back().nrb * tab.back().nsplit);
+                }
+                push_table(buf, tab, boff, gl);
+            }
+            gl.total = boff.back();
+            per_round[r].push_back(gl);
         }
     }
+    GF2_TRY(lead->sig_tab.ensure(std::max<size_t>(buf.size(), 16)));
+    GF2_HIP(hipMemcpyAsync(lead->sig_tab.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice,
+                           lead->stream));
+    // dynamic-LDS limits are set outside the capture
+    for (auto &v : per_round)
+        for (auto &gl : v)
+            if (gl.stage == 2) {
+                KRef<S23Args> r0{};
+                KRef<S23b3Args> r1{};
+                if (prec == MODE_BF3) GF2_TRY(launch_s23_bf3(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r1, true));
+                else if (prec == MODE_F64) GF2_TRY(launch_s23<MODE_F64>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
+                else GF2_TRY(launch_s23<MODE_F32>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
+            }
+    GF2_HIP(hipStreamSynchronize(lead->stream));
+    if (!lead->bat_cap) GF2_HIP(hipStreamCreateWithFlags(&lead->bat_cap, hipStreamNonBlocking));
+    hipStream_t st = lead->bat_cap;
+    unsigned char *tb = lead->sig_tab.as<unsigned char>();
+    hipGraph_t graph = nullptr;
+    GF2_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = GF2_OK;
+    for (int r = 0; r < rounds && rc == GF2_OK; ++r) {
+        for (int s = 0; s < ns && rc == GF2_OK; ++s) {
+            auto &p = plans[s];
+            if (r * p.sh.b < p.ntau) rc = plan_stage(p, st, r * p.sh.b, std::min(p.sh.b, p.ntau - r * p.sh.b));
+        }
+        for (auto &gl : per_round[r]) {
+            if (rc != GF2_OK) break;
+            const dim3 grid(xcd_grid(gl.total));
+            if (gl.stage == 1) {
+                KRef<GemmArgs> ref{};
+                ref.tab = reinterpret_cast<const GemmArgs *>(tb + gl.tab_off);
+                ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
+                ref.nsys = gl.nsys;
+                ref.total = gl.total;
+                rc = launch_s1(prec, gl.cls_a, gl.cls_b, grid, st, ref);
+            } else if (gl.stage == 2) {
+                if (prec == MODE_BF3) {
+                    KRef<S23b3Args> ref{};
+                    ref.tab = reinterpret_cast<const S23b3Args *>(tb + gl.tab_off);
+                    ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
+                    ref.nsys = gl.nsys;
+                    ref.total = gl.total;
+                    rc = launch_s23_bf3(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
+                } else {
+                    KRef<S23Args> ref{};
+                    ref.tab = reinterpret_cast<const S23Args *>(tb + gl.tab_off);
+                    ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
+                    ref.nsys = gl.nsys;
+                    ref.total = gl.total;
+                    if (prec == MODE_F64) rc = launch_s23<MODE_F64>(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
+                    else rc = launch_s23<MODE_F32>(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
+                }
+            } else {
+                if (prec == MODE_BF3) {
+                    KRef<S4b3Args> ref{};
+                    ref.tab = reinterpret_cast<const S4b3Args *>(tb + gl.tab_off);
+                    ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
+                    ref.nsys = gl.nsys;
+                    ref.total = gl.total;
+                    rc = launch_s4_bf3(st, gl.cls_a, grid, ref);
+                } else {
+                    KRef<S4Args> ref{};
+                    ref.tab = reinterpret_cast<const S4Args *>(tb + gl.tab_off);
+                    ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
+                    ref.nsys = gl.nsys;
+                    ref.total = gl.total;
+                    if (prec == MODE_F64) rc = launch_s4<MODE_F64>(st, gl.cls_a, grid, ref);
+                    else rc = launch_s4<MODE_F32>(st, gl.cls_a, grid, ref);
+                }
+            }
+        }
+        for (int s = 0; s < ns && rc == GF2_OK; ++s) {
+            auto &p = plans[s];
+            if (r * p.sh.b < p.ntau) rc = plan_reduce(p, st, r * p.sh.b, std::min(p.sh.b, p.ntau - r * p.sh.b));
+        }
+    }
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != GF2_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    GF2_HIP(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    GF2_HIP(ei);
+    lead->sig_graph = exec;
+    lead->sig_key = key;
+    GF2_HIP(hipGraphLaunch(exec, lead->stream));
     return GF2_OK;
+}
+
+void sigma_release(gf2_ctx *c) {
+    if (c->sig_graph) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(c->sig_graph));
+        c->sig_graph = nullptr;
+        c->sig_key = 0;
+    }
 }
 
 }  // namespace gf2

@@ -256,3 +256,27 @@ def test_density_fock_rejects_impossible_electron_count(torch):
         g.density_fock(make_params(), _dev(torch, s.h), 0.0)
     assert e.value.code == -5
     g.close()
+
+
+@pytest.mark.parametrize("n", [17, 40])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_sigma_shape_invariant(torch, n, prec):
+    """The tuned launch shape (tau batch, waves per S23 workgroup) moves work
+    between workgroups only: every shape gives bitwise the same Sigma(tau)."""
+    import os
+    print(f"sigma shapes n={n} prec={prec}", flush=True)
+    ntau = 11
+    s = generic_system(n, 900 + n, naux=2 * n, beta=20.0, ntau=ntau)
+    Gt = _dev(torch, random_tau_stack(np.random.default_rng(n), ntau, n))
+    g = _gf2(s)
+    outs = []
+    try:
+        for b, w in [(11, 4), (4, 8), (1, 16), (3, 4)]:
+            os.environ["GF2_SIGMA_SHAPE"] = f"{b},{w}"
+            outs.append(g.sigma_tau(Gt, prec).cpu().numpy())
+    finally:
+        os.environ.pop("GF2_SIGMA_SHAPE", None)
+    outs.append(g.sigma_tau(Gt, prec).cpu().numpy())   # tuned shape
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    g.close()
