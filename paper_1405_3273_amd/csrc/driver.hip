@@ -20,6 +20,7 @@
 //   loop, Galitskii-Migdal energy, G(tau).
 #include "gf2_internal.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -266,11 +267,91 @@ static bool solve_pivoted(int n, std::vector<double> A, std::vector<double> b,
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Inner-loop reductions and Pulay updates on the device.  Reduction results go
+// to a small device array (`red`, IL_RED doubles per system) that the caller
+// copies to the host; the batched driver copies the arrays of all systems in
+// one transfer, overlapped with the next Dyson round of the other systems.
+
+constexpr int IL_THREADS = 256;
+constexpr int IL_MAXDEPTH = 32;
+constexpr int IL_RED = 40;    // >= 1 + IL_MAXDEPTH
+
+struct SlotList {
+    int id[IL_MAXDEPTH];      // Pulay slots, oldest first
+    double c[IL_MAXDEPTH];    // mixing coefficients (k_pulay_mix)
+    int k;
+};
+
+// fixed-order block reduction (op 0: max, else sum) of one value per thread
+template <int OP>
+__device__ double block_reduce(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = IL_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            sh[threadIdx.x] = OP == 0 ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
+                                      : sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// red[0] = max_e |a[e] - b[e]|
+__global__ __launch_bounds__(IL_THREADS) void k_maxdiff(int ne, const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        double *__restrict__ red) {
+    __shared__ double sh[IL_THREADS];
+    double m = 0.0;
+    for (int e = threadIdx.x; e < ne; e += IL_THREADS) m = fmax(m, fabs(a[e] - b[e]));
+    m = block_reduce<0>(m, sh);
+    if (threadIdx.x == 0) red[0] = m;
+}
+
+// red[1 + j] = <r_s, r_{id[j]}> (one workgroup per j), r_o = slots + (2 o + 1) ne
+__global__ __launch_bounds__(IL_THREADS) void k_pulay_dots(int ne, int s, const double *__restrict__ slots,
+                                                           SlotList L, double *__restrict__ red) {
+    __shared__ double sh[IL_THREADS];
+    const double *rs = slots + (size_t)(2 * s + 1) * ne;
+    const double *ro = slots + (size_t)(2 * L.id[blockIdx.x] + 1) * ne;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < ne; e += IL_THREADS) acc += rs[e] * ro[e];
+    acc = block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) red[1 + blockIdx.x] = acc;
+}
+
+// slot s: x_s = P_in, r_s = P_out - P_in
+__global__ void k_pulay_push(int ne, const double *__restrict__ Pin, const double *__restrict__ Pout,
+                             double *__restrict__ xs) {
+    double *rs = xs + ne;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        const double x = Pin[e];
+        xs[e] = x;
+        rs[e] = Pout[e] - x;
+    }
+}
+
+// P_next = sum_a c_a (x_a + (1 - damp) r_a)   (may overwrite P_in: reads only slots)
+__global__ void k_pulay_mix(int ne, const double *__restrict__ slots, SlotList L, double damp,
+                            double *__restrict__ Pnext) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int a = 0; a < L.k; ++a) {
+            const double *x = slots + (size_t)(2 * L.id[a]) * ne;
+            acc = fma(L.c[a], fma(1.0 - damp, x[ne + e], x[e]), acc);
+        }
+        Pnext[e] = acc;
+    }
+}
+
+static unsigned grid_for(size_t ne) { return (unsigned)std::min<size_t>((ne + 255) / 256, 1024); }
+
 struct Pulay {
     int depth = 1;
     // device slots: x_a, r_a (ring of depth entries), host B_ab = <r_a, r_b>
     std::vector<int> order;          // slot ids, oldest first
     std::vector<double> B;           // depth x depth, indexed by slot
+    int last = -1;                   // slot pushed last
     int free_slot() const {
         for (int s = 0; s < depth; ++s) {
             bool used = false;
@@ -279,87 +360,61 @@ struct Pulay {
         }
         return -1;
     }
+    // coefficients c (sum c_a = 1) minimising |sum c_a r_a|; a singular
+    // system drops all but the newest pair
+    std::vector<double> coef() {
+        for (;;) {
+            const int k = (int)order.size();
+            std::vector<double> A((k + 1) * (k + 1), 0.0), rhs(k + 1, 0.0), sol;
+            double dmax = 0.0;
+            for (int a = 0; a < k; ++a) dmax = std::fmax(dmax, B[order[a] * (depth + 1)]);
+            dmax = std::fmax(dmax, 1e-300);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) A[a * (k + 1) + b] = B[order[a] * depth + order[b]] / dmax;
+            for (int a = 0; a < k; ++a) {
+                A[k * (k + 1) + a] = 1.0;
+                A[a * (k + 1) + k] = 1.0;
+            }
+            rhs[k] = 1.0;
+            if (solve_pivoted(k + 1, A, rhs, sol)) return std::vector<double>(sol.begin(), sol.begin() + k);
+            if (k == 1) return std::vector<double>(1, 1.0);
+            order.erase(order.begin(), order.end() - 1);
+        }
+    }
 };
 
-static int pulay_step(gf2_ctx *c, Pulay &pl, double *slots, size_t ne, const double *P_in,
-                      const double *r, double damp, double *P_next) {
-    // push (P_in, r), dropping the oldest beyond depth
-    if ((int)pl.order.size() == pl.depth) pl.order.erase(pl.order.begin());
-    const int s = pl.free_slot();
-    double *xs = slots + (size_t)(2 * s) * ne, *rs = xs + ne;
-    GF2_TRY(copy_d2d(c, xs, P_in, ne * 8));
-    GF2_TRY(copy_d2d(c, rs, r, ne * 8));
-    pl.order.push_back(s);
-    for (int o : pl.order) {
-        double v;
-        GF2_TRY(dot(c, ne, rs, slots + (size_t)(2 * o + 1) * ne, &v));
-        pl.B[s * pl.depth + o] = v;
-        pl.B[o * pl.depth + s] = v;
-    }
-    std::vector<double> coef;
-    for (;;) {
-        const int k = (int)pl.order.size();
-        std::vector<double> A((k + 1) * (k + 1), 0.0), rhs(k + 1, 0.0), sol;
-        double dmax = 0.0;
-        for (int a = 0; a < k; ++a) dmax = std::fmax(dmax, pl.B[pl.order[a] * (pl.depth + 1)]);
-        dmax = std::fmax(dmax, 1e-300);
-        for (int a = 0; a < k; ++a)
-            for (int b = 0; b < k; ++b)
-                A[a * (k + 1) + b] = pl.B[pl.order[a] * pl.depth + pl.order[b]] / dmax;
-        for (int a = 0; a < k; ++a) {
-            A[k * (k + 1) + a] = 1.0;
-            A[a * (k + 1) + k] = 1.0;
-        }
-        rhs[k] = 1.0;
-        if (solve_pivoted(k + 1, A, rhs, sol)) {
-            coef.assign(sol.begin(), sol.begin() + k);
-            break;
-        }
-        if (k == 1) {
-            coef.assign(1, 1.0);
-            break;
-        }
-        pl.order.erase(pl.order.begin(), pl.order.end() - 1);
-    }
-    // P_next = sum_a c_a (x_a + (1 - damp) r_a)
-    GF2_TRY(fill_zero(c, P_next, ne * 8));
-    double *tmp = c->it_tmp.as<double>() + 1024;   // scratch after the reduction area
-    for (size_t a = 0; a < coef.size(); ++a) {
-        const int o = pl.order[a];
-        const double *xa = slots + (size_t)(2 * o) * ne, *ra = xa + ne;
-        GF2_TRY(copy_d2d(c, tmp, xa, ne * 8));
-        GF2_TRY(axpby(c, ne, 1.0 - damp, ra, 1.0, tmp));
-        GF2_TRY(axpby(c, ne, coef[a], tmp, 1.0, P_next));
-    }
-    return GF2_OK;
-}
-
 // The inner loop (steps 2.a-2.b) of one system as a state machine.  Phase 0:
-// the mu search wants N(ms.pending) (a TRACE solve); phase 1: the density
+// the mu search wants N(ms.pending) (a density-mode solve, see on_eval); phase 1: the density
 // pass wants a FULL (ENERGY when Sigma is set) solve at mu writing P_out,
-// G(i w) and the tail moments; phase 2: converged.  The single-system loop
-// and the batched driver feed it the same solves in the same order.
+// G(i w) and the tail moments; phase 3: device reductions were enqueued into
+// `red` and on_red wants their values (want 1: max|P_out - P_in|; want 2: the
+// Pulay dots); phase 2: converged.  The single-system loop and the batched
+// driver feed it the same solves and reductions in the same order.
 struct InnerLoop {
     gf2_ctx *c = nullptr;
     const gf2_dims *d = nullptr;
     const gf2_params *p = nullptr;
     const double2 *Sig = nullptr;
     const double *Sig1 = nullptr;
-    double *Pin = nullptr, *Pout = nullptr, *F = nullptr, *slots = nullptr, *r = nullptr;
+    double *Pin = nullptr, *Pout = nullptr, *F = nullptr, *slots = nullptr;
     double *mom = nullptr;
+    double *red = nullptr;
     double2 *G_iw = nullptr;
     Pulay pl;
     MuSearch ms;
     bool have_Pin = false;
     double mu = 0.0, slope = 0.0, trPS = 0.0, e2b = 0.0;
-    int it = 0, n_inner = 0, n_eval = 0, phase = 0;
+    int it = 0, n_inner = 0, n_eval = 0, phase = 0, want = 0;
 
     int density_mode() const { return Sig ? GF2_DYSON_ENERGY : GF2_DYSON_FULL; }
+    // doubles of `red` that on_red reads
+    int red_count() const { return want == 1 ? 1 : 1 + (int)pl.order.size(); }
 
-    // workspaces and starting point (P from the state if present, F, mu)
+    // workspaces and starting point (P from the state if present, F, mu);
+    // red_dev: IL_RED doubles of device memory for the reductions
     int start(gf2_ctx *ctx, const gf2_dims *dd, const gf2_params *pp, const gf2_state *st,
-              const double2 *sig, const double *sig1) {
-        c = ctx; d = dd; p = pp; Sig = sig; Sig1 = sig1;
+              const double2 *sig, const double *sig1, double *red_dev) {
+        c = ctx; d = dd; p = pp; Sig = sig; Sig1 = sig1; red = red_dev;
         const size_t ne = (size_t)c->n * c->n;
         GF2_TRY(c->it_Pout.ensure(ne * 8));
         GF2_TRY(c->it_Pin.ensure(ne * 8));
@@ -367,14 +422,12 @@ struct InnerLoop {
         GF2_TRY(c->it_mom.ensure(3 * ne * 8));
         GF2_TRY(c->it_G_iw.ensure((size_t)d->niw * ne * 16));
         GF2_TRY(c->it_hist.ensure((size_t)2 * p->mix_depth * ne * 8));
-        GF2_TRY(c->it_tmp.ensure((1024 + 2 * ne) * 8));
         Pin = c->it_Pin.as<double>();
         Pout = c->it_Pout.as<double>();
         F = c->it_F.as<double>();
         mom = c->it_mom.as<double>();
         G_iw = c->it_G_iw.as<double2>();
         slots = c->it_hist.as<double>();
-        r = c->it_tmp.as<double>() + 1024 + ne;   // pulay_step uses [1024, 1024 + ne)
         have_Pin = st->has_P != 0;
         if (have_Pin) GF2_TRY(copy_d2d(c, Pin, st->P, ne * 8));
         GF2_TRY(copy_d2d(c, F, st->F, ne * 8));
@@ -386,40 +439,90 @@ struct InnerLoop {
         it = 1;
         n_inner = n_eval = 0;
         phase = 0;
+        want = 0;
         ms.start(p, mu, slope);
         return GF2_OK;
     }
-    // result of the TRACE solve at ms.pending
-    int on_trace(double trps) {
-        GF2_TRY(ms.feed(trps - (double)d->nelec));
+    // result of the phase-0 solve at ms.pending.  That solve runs in the
+    // density mode: trace_n is what a TRACE solve would give (the search
+    // sees the same values), and when the search accepts the point just
+    // evaluated its P, G(i w) and moments are already in place, so the
+    // density solve at mu is skipped.
+    int on_eval(double trace_n, double trps, double e2) {
+        const double x = ms.pending;
+        GF2_TRY(ms.feed(trace_n - (double)d->nelec));
         if (ms.done) {
             mu = ms.mu;
             if (ms.have_slope) slope = ms.slope;
             phase = 1;
+            if (ms.mu == x) return on_density(trps, e2);
         }
         return GF2_OK;
     }
     // the density solve at mu has written Pout, G_iw and mom
     int on_density(double trps, double e2) {
-        const size_t ne = (size_t)c->n * c->n;
+        const int ne = c->n * c->n;
         trPS = trps;
         e2b = e2;
         n_eval += ms.evals;
         n_inner = it;
         if (!have_Pin) {
-            GF2_TRY(copy_d2d(c, Pin, Pout, ne * 8));
+            GF2_TRY(copy_d2d(c, Pin, Pout, (size_t)ne * 8));
             have_Pin = true;
-        } else {
-            double dmax;
-            GF2_TRY(max_abs_diff(c, ne, Pout, Pin, &dmax));
-            if (dmax < p->tol_P) {
+            return next_iteration();
+        }
+        hipLaunchKernelGGL(k_maxdiff, dim3(1), dim3(IL_THREADS), 0, c->stream, ne, Pout, Pin, red);
+        GF2_HIP(hipGetLastError());
+        phase = 3;
+        want = 1;
+        return GF2_OK;
+    }
+    // h: the first red_count() values of `red`
+    int on_red(const double *h) {
+        const int ne = c->n * c->n;
+        if (want == 1) {
+            if (h[0] < p->tol_P) {
                 phase = 2;
+                want = 0;
                 return GF2_OK;
             }
-            GF2_TRY(copy_d2d(c, r, Pout, ne * 8));
-            GF2_TRY(axpby(c, ne, -1.0, Pin, 1.0, r));
-            GF2_TRY(pulay_step(c, pl, slots, ne, Pin, r, p->damp_P, Pin));
+            // push (P_in, r = P_out - P_in), dropping the oldest beyond depth
+            if ((int)pl.order.size() == pl.depth) pl.order.erase(pl.order.begin());
+            const int s = pl.free_slot();
+            hipLaunchKernelGGL(k_pulay_push, dim3(grid_for(ne)), dim3(256), 0, c->stream, ne, Pin, Pout,
+                               slots + (size_t)(2 * s) * ne);
+            pl.order.push_back(s);
+            pl.last = s;
+            SlotList L{};
+            L.k = (int)pl.order.size();
+            for (int a = 0; a < L.k; ++a) L.id[a] = pl.order[a];
+            hipLaunchKernelGGL(k_pulay_dots, dim3(L.k), dim3(IL_THREADS), 0, c->stream, ne, s, slots,
+                               L, red);
+            GF2_HIP(hipGetLastError());
+            want = 2;
+            return GF2_OK;
         }
+        // want == 2: B row/column of the new slot, then the mixed P_in
+        const int s = pl.last;
+        for (size_t a = 0; a < pl.order.size(); ++a) {
+            const int o = pl.order[a];
+            pl.B[s * pl.depth + o] = h[1 + a];
+            pl.B[o * pl.depth + s] = h[1 + a];
+        }
+        const std::vector<double> cf = pl.coef();
+        SlotList L{};
+        L.k = (int)cf.size();
+        for (int a = 0; a < L.k; ++a) {
+            L.id[a] = pl.order[a];
+            L.c[a] = cf[a];
+        }
+        hipLaunchKernelGGL(k_pulay_mix, dim3(grid_for(ne)), dim3(256), 0, c->stream, ne, slots, L,
+                           p->damp_P, Pin);
+        GF2_HIP(hipGetLastError());
+        want = 0;
+        return next_iteration();
+    }
+    int next_iteration() {
         GF2_TRY(fock_run(c, Pin, F));
         if (++it > p->max_inner) return fail(GF2_ENOCONV, "gf2_iterate: inner loop did not converge");
         ms.start(p, mu, slope);
@@ -597,18 +700,25 @@ extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, g
     GF2_TRY(iter_sigma(c, d, p, st, &Sig, &Sig1, &t_sig, &t_four));
 
     const double ti = now_ms();
+    GF2_TRY(c->it_red.ensure(IL_RED * 8));
     InnerLoop il;
-    GF2_TRY(il.start(c, d, p, st, Sig, Sig1));
+    GF2_TRY(il.start(c, d, p, st, Sig, Sig1, c->it_red.as<double>()));
     while (il.phase != 2) {
         double r2[2];
         if (il.phase == 0) {
-            GF2_TRY(dyson_run(c, d, GF2_DYSON_TRACE, il.ms.pending, il.F, Sig, nullptr, nullptr,
-                              nullptr, nullptr, r2));
-            GF2_TRY(il.on_trace(r2[0]));
-        } else {
+            double tn;
+            GF2_TRY(dyson_run(c, d, il.density_mode(), il.ms.pending, il.F, Sig, Sig1, il.G_iw,
+                              il.Pout, il.mom, r2, &tn));
+            GF2_TRY(il.on_eval(tn, r2[0], r2[1]));
+        } else if (il.phase == 1) {
             GF2_TRY(dyson_run(c, d, il.density_mode(), il.mu, il.F, Sig, Sig1, il.G_iw, il.Pout,
                               il.mom, r2));
             GF2_TRY(il.on_density(r2[0], r2[1]));
+        } else {
+            double h[IL_RED];
+            GF2_HIP(hipMemcpyAsync(h, il.red, il.red_count() * 8, hipMemcpyDeviceToHost, c->stream));
+            GF2_HIP(hipStreamSynchronize(c->stream));
+            GF2_TRY(il.on_red(h));
         }
     }
     const double t_inner_end = now_ms();
@@ -684,27 +794,38 @@ extern "C" int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dim
     }
 
     const double ti = now_ms();
+    // reduction arrays of all systems side by side, copied to pinned memory at once
+    GF2_TRY(lead->bat_red.ensure((size_t)nsys * IL_RED * 8));
+    const size_t red_bytes = (size_t)nsys * IL_RED * 8;
+    if (lead->bat_red_h_bytes < red_bytes) {
+        if (lead->bat_red_h) (void)hipHostFree(lead->bat_red_h);
+        lead->bat_red_h = nullptr;
+        lead->bat_red_h_bytes = 0;
+        GF2_HIP(hipHostMalloc(&lead->bat_red_h, red_bytes, hipHostMallocDefault));
+        lead->bat_red_h_bytes = red_bytes;
+    }
+    double *red_h = static_cast<double *>(lead->bat_red_h);
     std::vector<InnerLoop> il(nsys);
     for (int s = 0; s < nsys; ++s)
-        GF2_TRY(il[s].start(ctxs[s], &dims[s], p, &states[s], Sig[s], Sig1[s]));
+        GF2_TRY(il[s].start(ctxs[s], &dims[s], p, &states[s], Sig[s], Sig1[s],
+                            lead->bat_red.as<double>() + (size_t)s * IL_RED));
     std::vector<DysonReq> req(nsys);
     std::vector<double> res;
+    std::vector<char> red_wait(nsys);
     for (;;) {
-        bool any = false;
+        bool any = false, any_red = false;
         for (int s = 0; s < nsys; ++s) {
+            red_wait[s] = il[s].phase == 3;
+            any_red |= red_wait[s] != 0;
             DysonReq &q = req[s];
             q = DysonReq{};
             q.c = ctxs[s];
             q.d = &dims[s];
             q.F = il[s].F;
             q.Sig = Sig[s];
-            if (il[s].phase == 0) {
-                q.mode = GF2_DYSON_TRACE;
-                q.mu = il[s].ms.pending;
-                any = true;
-            } else if (il[s].phase == 1) {
+            if (il[s].phase == 0 || il[s].phase == 1) {
                 q.mode = il[s].density_mode();
-                q.mu = il[s].mu;
+                q.mu = il[s].phase == 0 ? il[s].ms.pending : il[s].mu;
                 q.Sig1 = Sig1[s];
                 q.G_iw = il[s].G_iw;
                 q.P = il[s].Pout;
@@ -714,11 +835,19 @@ extern "C" int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dim
                 q.mode = -1;
             }
         }
-        if (!any) break;
-        GF2_TRY(dyson_round(lead, req, res));
+        if (!any && !any_red) break;
+        // the pending reductions come back with the round of the other systems
+        if (any_red)
+            GF2_HIP(hipMemcpyAsync(red_h, lead->bat_red.ptr, red_bytes, hipMemcpyDeviceToHost,
+                                   lead->stream));
+        if (any) GF2_TRY(dyson_round(lead, req, res));
+        else GF2_HIP(hipStreamSynchronize(lead->stream));
         for (int s = 0; s < nsys; ++s) {
-            if (req[s].mode == GF2_DYSON_TRACE) GF2_TRY(il[s].on_trace(res[2 * s]));
-            else if (req[s].mode > GF2_DYSON_TRACE) GF2_TRY(il[s].on_density(res[2 * s], res[2 * s + 1]));
+            const double *r = &res[(size_t)3 * s];
+            if (red_wait[s]) GF2_TRY(il[s].on_red(red_h + (size_t)s * IL_RED));
+            else if (req[s].mode < 0) continue;
+            else if (il[s].phase == 0) GF2_TRY(il[s].on_eval(r[2], r[0], r[1]));
+            else GF2_TRY(il[s].on_density(r[0], r[1]));
         }
     }
     const double t_inner = now_ms() - ti;

@@ -46,7 +46,9 @@ struct DysonJob {
     double *P;              // FULL/ENERGY output
     double *mom;            // [3][n][n] tail moments G1, G2, G3 (computed here)
     double *scr;            // [3][n][n] scratch
-    double *partP;          // [nbl][n*n]   (FULL/ENERGY)
+    double *partP;          // [nbl][n*n]   (FULL/ENERGY) per-slot P accumulators
+    double *partW;          // [npw][n*n]   per-workgroup P partials that k_reduce_P sums
+    int npw;
     double *parts;          // [nbl][4]     (trace, energy, singular flag)
     double *out;            // [5] reduced results
 };
@@ -268,9 +270,8 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 if (!(active && i < n && j < n)) continue;
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
-                if (!full) {
-                    acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
-                } else {
+                acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
+                if (full) {
                     Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
                     if (a.mode == GF2_DYSON_ENERGY && Sig) {
@@ -481,9 +482,8 @@ __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, cons
                 if (!(i < n && j < n)) continue;
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
-                if (!full) {
-                    acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
-                } else {
+                acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
+                if (full) {
                     Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
                     if (a.mode == GF2_DYSON_ENERGY && Sig) {
@@ -506,9 +506,17 @@ __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, cons
         ps[2] = (double)sing;
         ps[3] = 0.0;
     }
-    if (full && a.p_in_lds) {
-        wave_sync();
-        for (int e = lane; e < n * n; e += 64) a.partP[(size_t)slot * n * n + e] = Pacc[e];
+    if (full) {
+        // the DW slots of this workgroup into one partial, waves in order
+        __syncthreads();
+        const int ne = n * n;
+        double *dst = a.partW + (size_t)lb * ne;
+        for (int e = tid; e < ne; e += 64 * DW) {
+            double s = 0.0;
+            for (int w = 0; w < DW; ++w)
+                s += a.p_in_lds ? shP[(size_t)w * ne + e] : a.partP[(size_t)(lb * DW + w) * ne + e];
+            dst[e] = s;
+        }
     }
 }
 
@@ -592,21 +600,43 @@ static void launch_moments(const DysonRef &g, int njobs, int maxne, hipStream_t 
         hipLaunchKernelGGL(k_moments, grid, dim3(256), 0, st, g, stage);
 }
 
-// P = (4/beta) sum_b partP[b] + G1 - (beta/2) G2   (grid: x over elements, y over jobs)
-__global__ void k_reduce_P(DysonRef g) {
+// P = (4/beta) sum_b partW[b] + G1 - (beta/2) G2.  Grid: x over 64-element
+// chunks, y over jobs; the four waves of a workgroup sum quarters of the
+// partials (four interleaved accumulators each) and are combined in order.
+__global__ __launch_bounds__(256) void k_reduce_P(DysonRef g) {
     const DysonJob a = job_of(g, blockIdx.y);
     if (a.mode <= GF2_DYSON_TRACE) return;
     const int ne = a.n * a.n;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ne) return;
-    double s = 0.0;
-    for (int b = 0; b < a.nbl; ++b) s += a.partP[(size_t)b * ne + e];
-    a.P[e] = (4.0 / a.beta) * s + a.mom[e] - 0.5 * a.beta * a.mom[ne + e];
+    if ((int)blockIdx.x * 64 >= ne) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 64 + lane;
+    __shared__ double sh[4][64];
+    const int q = (a.npw + 3) / 4;
+    const int b0 = wv * q, b1 = min(a.npw, b0 + q);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < ne) {
+        const double *p = a.partW + e;
+        int b = b0;
+        for (; b + 4 <= b1; b += 4) {
+            s0 += p[(size_t)b * ne];
+            s1 += p[(size_t)(b + 1) * ne];
+            s2 += p[(size_t)(b + 2) * ne];
+            s3 += p[(size_t)(b + 3) * ne];
+        }
+        for (; b < b1; ++b) s0 += p[(size_t)b * ne];
+    }
+    sh[wv][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (wv == 0 && e < ne) {
+        const double s = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+        a.P[e] = (4.0 / a.beta) * s + a.mom[e] - 0.5 * a.beta * a.mom[ne + e];
+    }
 }
 
 // out[0] = sum_b parts[b][0], out[1] = sum parts[b][1], out[2] = max flag,
-// out[3] = <X, Y> (Frobenius), out[4] = <U, V>; TRACE: X = G2, Y = S;
-// FULL/ENERGY: X = P, Y = S, U = G1, V = Sig1 (ENERGY with Sig1).  One workgroup per job.
+// out[3] = <X, Y> (Frobenius), out[4] = <U, V>, out[5] = <G2, S>; TRACE: X = G2,
+// Y = S; FULL/ENERGY: X = P, Y = S, U = G1, V = Sig1 (ENERGY with Sig1).  One
+// workgroup per job.
 __global__ __launch_bounds__(256) void k_finish(DysonRef g) {
     const DysonJob a = job_of(g, blockIdx.x);
     if (a.mode < 0) return;
@@ -616,9 +646,9 @@ __global__ __launch_bounds__(256) void k_finish(DysonRef g) {
     const double *Y = a.S;
     const double *U = (a.mode == GF2_DYSON_ENERGY && a.Sig1) ? a.mom : nullptr;
     const double *V = a.Sig1;
-    __shared__ double sh[5][256];
+    __shared__ double sh[6][256];
     const int t = threadIdx.x;
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
     for (int b = t; b < a.nbl; b += 256) {
         a0 += a.parts[(size_t)b * 4];
         a1 += a.parts[(size_t)b * 4 + 1];
@@ -627,7 +657,9 @@ __global__ __launch_bounds__(256) void k_finish(DysonRef g) {
     for (int e = t; e < ne; e += 256) a3 += X[e] * Y[e];
     if (U && V)
         for (int e = t; e < ne; e += 256) a4 += U[e] * V[e];
-    sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = a3; sh[4][t] = a4;
+    if (full)
+        for (int e = t; e < ne; e += 256) a5 += a.mom[ne + e] * Y[e];
+    sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = a3; sh[4][t] = a4; sh[5][t] = a5;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (t < s) {
@@ -636,10 +668,11 @@ __global__ __launch_bounds__(256) void k_finish(DysonRef g) {
             sh[2][t] = fmax(sh[2][t], sh[2][t + s]);
             sh[3][t] += sh[3][t + s];
             sh[4][t] += sh[4][t + s];
+            sh[5][t] += sh[5][t + s];
         }
         __syncthreads();
     }
-    if (t < 5) a.out[t] = sh[t][0];
+    if (t < 6) a.out[t] = sh[t][0];
 }
 
 // attr_only: set the dynamic-LDS limit without launching (before a capture)
@@ -716,7 +749,43 @@ static size_t dyson_shm(int n, int mode) {
     return need <= 32 * 1024 ? need : 0;
 }
 
-// Host part of a job's result: h = out[0..4] of k_finish
+// P partials of a FULL/ENERGY solve: the wave class sums the DW slots of a
+// workgroup into one partial (after the per-slot accumulators when those are
+// in global memory); the workgroup class writes one partial per workgroup.
+struct PartLayout {
+    size_t bytes;   // dys_part size
+    size_t off_w;   // element offset of the per-workgroup partials
+    int npw;        // their count
+};
+static PartLayout part_layout(int n, int slots, int mode) {
+    const size_t ne = (size_t)n * n;
+    PartLayout L{};
+    if (dyson_wave_class(dyson_class(n))) {
+        L.npw = slots / DW;
+        L.off_w = dyson_shm(n, mode) > 0 ? 0 : (size_t)slots * ne;
+    } else {
+        L.npw = slots;
+        L.off_w = 0;
+    }
+    L.bytes = (L.off_w + (size_t)L.npw * ne) * 8;
+    return L;
+}
+
+// N(mu) + n... : tr(P S) from the per-frequency traces tr(G(i w) S) and the
+// tail: (4/beta) (sum_n Re tr(G S) + tr(G2 S) sum_n 1/w_n^2) + n - (beta/2) tr(G2 S)
+static double trace_formula(const DysonJob &j, double sum_tr, double trG2S) {
+    const double beta = j.beta;
+    double sw = 0.0;   // sum_{n<niw} 1/w_n^2
+    for (int k = 0; k < j.niw; ++k) {
+        const double w = M_PI * (double)(2 * k + 1) / beta;
+        sw += 1.0 / (w * w);
+    }
+    return (4.0 / beta) * (sum_tr + trG2S * sw) + (double)j.n - 0.5 * beta * trG2S;
+}
+
+// Host part of a job's result: h = out[0..5] of k_finish.  out[0]: tr(P S)
+// (FULL/ENERGY: of the assembled P; TRACE: the trace formula), out[1]: the
+// energy term, out[2]: the trace formula in every mode.
 static int dyson_post(const DysonJob &j, const double *h, double *out) {
     if (h[2] != 0.0) return fail(GF2_ENONFINITE, "gf2_dyson: singular or non-finite matrix");
     const double beta = j.beta;
@@ -729,24 +798,20 @@ static int dyson_post(const DysonJob &j, const double *h, double *out) {
                                 trigamma(j.niw + 0.5);
             out[1] = (2.0 / beta) * h[1] + tail;
         }
+        out[2] = trace_formula(j, h[0], h[5]);
     } else {
-        double sw = 0.0;   // sum_{n<niw} 1/w_n^2
-        for (int k = 0; k < j.niw; ++k) {
-            const double w = M_PI * (double)(2 * k + 1) / beta;
-            sw += 1.0 / (w * w);
-        }
-        const double trG2S = h[3];
-        out[0] = (4.0 / beta) * (h[0] + trG2S * sw) + (double)j.n - 0.5 * beta * trG2S;
+        out[0] = trace_formula(j, h[0], h[3]);
         out[1] = 0.0;
+        out[2] = out[0];
     }
-    if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1]) || !std::isfinite(out[2]))
         return fail(GF2_ENONFINITE, "gf2_dyson: non-finite result");
     return GF2_OK;
 }
 
 int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
               const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
-              double *mom_out, double *out) {
+              double *mom_out, double *out, double *trace_n) {
     const int n = c->n, niw = d->niw;
     const size_t ne = (size_t)n * n;
     if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
@@ -758,7 +823,8 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     GF2_TRY(c->dys_X.ensure(6 * ne * 8));
     GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
     GF2_TRY(c->dys_out.ensure(8 * 8));
-    if (full) GF2_TRY(c->dys_part.ensure((size_t)nblocks * ne * 8));
+    const PartLayout pl = part_layout(n, nblocks, mode);
+    if (full) GF2_TRY(c->dys_part.ensure(pl.bytes));
 
     DysonRef g{};
     DysonJob &a = g.one;
@@ -773,6 +839,8 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     a.mom = c->dys_X.as<double>();
     a.scr = a.mom + 3 * ne;
     a.partP = full ? c->dys_part.as<double>() : nullptr;
+    a.partW = full ? c->dys_part.as<double>() + pl.off_w : nullptr;
+    a.npw = pl.npw;
     a.parts = c->dys_aux.as<double>();
     a.out = c->dys_out.as<double>();
     g.nsys = 0;
@@ -783,15 +851,19 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     prof_end(c, ph, 8.0 * (double)n * n * n * niw);
     GF2_HIP(hipGetLastError());
     if (full)
-        hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((ne + 255) / 256), 1), dim3(256), 0,
+        hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((ne + 63) / 64), 1), dim3(256), 0,
                            c->stream, g);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, g);
     GF2_HIP(hipGetLastError());
     if (mom_out) GF2_TRY(copy_d2d(c, mom_out, a.mom, 3 * ne * 8));
-    double h[5];
-    GF2_HIP(hipMemcpyAsync(h, a.out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double h[6], o[3];
+    GF2_HIP(hipMemcpyAsync(h, a.out, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     GF2_HIP(hipStreamSynchronize(c->stream));
-    return dyson_post(a, h, out);
+    GF2_TRY(dyson_post(a, h, o));
+    out[0] = o[0];
+    out[1] = o[1];
+    if (trace_n) *trace_n = o[2];
+    return GF2_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -850,7 +922,7 @@ static int enqueue_round(gf2_ctx *lead, hipStream_t st, const RoundShape &sh, in
         const int nblk = sh.boff[sh.cls_begin[k + 1] + k];
         GF2_TRY(launch_dyson_class(sh.cls_ra[k], dim3(nblk), sh.shm[k], st, g));
     }
-    hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((maxne + 255) / 256), (unsigned)nsys), dim3(256),
+    hipLaunchKernelGGL(k_reduce_P, dim3((unsigned)((maxne + 63) / 64), (unsigned)nsys), dim3(256),
                        0, st, all);
     hipLaunchKernelGGL(k_finish, dim3(nsys), dim3(256), 0, st, all);
     GF2_HIP(hipGetLastError());
@@ -859,7 +931,7 @@ static int enqueue_round(gf2_ctx *lead, hipStream_t st, const RoundShape &sh, in
 
 int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<double> &res) {
     const int nsys = (int)req.size();
-    res.assign((size_t)2 * nsys, 0.0);
+    res.assign((size_t)3 * nsys, 0.0);
     // shape: systems ordered by size class (stable), workgroups per job
     RoundShape sh;
     std::vector<int> ra(nsys), nbl(nsys);
@@ -902,7 +974,7 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
         const size_t ne = (size_t)c->n * c->n;
         GF2_TRY(c->dys_X.ensure(6 * ne * 8));
         GF2_TRY(c->dys_aux.ensure((size_t)nbl[s] * 4 * 8 + 64));
-        GF2_TRY(c->dys_part.ensure((size_t)nbl[s] * ne * 8));
+        GF2_TRY(c->dys_part.ensure(part_layout(req[s].c->n, nbl[s], GF2_DYSON_FULL).bytes));
     }
     const size_t tab_bytes = (size_t)nsys * sizeof(DysonJob);
     const size_t boff_bytes = sh.boff.size() * sizeof(int);
@@ -947,7 +1019,10 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
         a.P = full ? q.P : nullptr;
         a.mom = (full && q.mom) ? q.mom : c->dys_X.as<double>();
         a.scr = c->dys_X.as<double>() + 3 * ne;
+        const PartLayout pl = part_layout(n, nbl[s], full ? q.mode : GF2_DYSON_FULL);
         a.partP = c->dys_part.as<double>();
+        a.partW = a.partP + pl.off_w;
+        a.npw = pl.npw;
         a.parts = c->dys_aux.as<double>();
         a.out = out_d + (size_t)t * 8;
         tab_h[t] = a;
@@ -995,7 +1070,7 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
     for (int t = 0; t < nsys; ++t) {
         const int s = sh.order[t];
         if (req[s].mode < 0) continue;
-        GF2_TRY(dyson_post(tab_h[t], out_h + (size_t)t * 8, &res[(size_t)2 * s]));
+        GF2_TRY(dyson_post(tab_h[t], out_h + (size_t)t * 8, &res[(size_t)3 * s]));
     }
     return GF2_OK;
 }

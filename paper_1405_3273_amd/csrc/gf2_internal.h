@@ -83,6 +83,10 @@ struct gf2_ctx {
     gf2::DevBuf fock_part;
     gf2::DevBuf it_Sig_iw, it_G_iw, it_Sig1, it_mom, it_Sig_new, it_Pout, it_Pin, it_F, it_tmp;
     gf2::DevBuf it_hist;                  // Pulay history on the device: [2*depth][n][n]
+    gf2::DevBuf it_red;                   // inner-loop reduction results
+    gf2::DevBuf bat_red;                  // the same for every system of a batch
+    void *bat_red_h = nullptr;            // pinned copy of bat_red
+    size_t bat_red_h_bytes = 0;
     // batched sweeps (gf2_iterate_batched, owned by the first context of the batch)
     gf2::DevBuf bat_tab, bat_boff, bat_out;
     void *bat_host = nullptr;             // pinned staging (hipHostMalloc)
@@ -145,17 +149,19 @@ int fourier_iw2tau(gf2_ctx *c, const gf2_dims *d, const double2 *G_iw, const dou
 
 // Dyson over all frequencies.  mode = GF2_DYSON_*.  out[0] = tr(PS),
 // out[1] = E_2b (ENERGY).  If mom_out != NULL the tail moments G1,G2,G3
-// of this (mu, F, Sigma_1) are written there ([3][n][n]).
+// of this (mu, F, Sigma_1) are written there ([3][n][n]).  trace_n (may be
+// NULL): tr(PS) by the formula of the TRACE mode, bitwise what a TRACE solve
+// at the same mu returns, in every mode.
 int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
               const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
-              double *mom_out, double *out);
+              double *mom_out, double *out, double *trace_n = nullptr);
 
 int fock_run(gf2_ctx *c, const double *P, double *F);
 
 // One round of Dyson solves for several systems (batched driver).  Job s:
 // mode (GF2_DYSON_*, or -1 to skip), mu, F, Sigma(i w), Sigma_1, and for
-// FULL/ENERGY the outputs G(i w), P and the tail moments.  res[s][0..1] as
-// the out[] of dyson_run.  All systems run on lead->stream.
+// FULL/ENERGY the outputs G(i w), P and the tail moments.  res[3 s + 0..1] as
+// the out[] of dyson_run, res[3 s + 2] as its trace_n.  All systems run on lead->stream.
 struct DysonReq {
     gf2_ctx *c;
     const gf2_dims *d;
