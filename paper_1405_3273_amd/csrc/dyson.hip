@@ -76,13 +76,20 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return fma(y, e, y);
 }
 
-// 1/a for complex a, scaled so that |a|^2 cannot overflow or underflow
+// 1/a for complex a: a scaled by the power of two 2^-e of its larger part
+// (exact), so |a|^2 of the scaled value lies in [1/4, 2); 1/a = 2^-e conj(a')/|a'|^2
 __device__ __forceinline__ double2 cinv(double2 a) {
-    const double s = fmax(fabs(a.x), fabs(a.y));
-    const double is = rcp_nr(s);
-    const double ar = a.x * is, ai = a.y * is;
-    const double id = rcp_nr(ar * ar + ai * ai) * is;
-    return make_double2(ar * id, -ai * id);
+    int e;
+    (void)frexp(fmax(fabs(a.x), fabs(a.y)), &e);
+    const double ar = ldexp(a.x, -e), ai = ldexp(a.y, -e);
+    const double id = rcp_nr(fma(ar, ar, ai * ai));
+    return make_double2(ldexp(ar * id, -e), ldexp(-ai * id, -e));
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Rotate a value by k lanes within each row of 16 lanes (DPP row_ror:k).
@@ -98,7 +105,7 @@ template <int K> __device__ __forceinline__ double ror16(double v) {
 template <int K> __device__ __forceinline__ void argmax_step(double &best, int &bi) {
     const double ob = ror16<K>(best);
     const int oi = ror16<K>(bi);
-    const bool take = ob > best || (ob == best && oi < bi);
+    const bool take = (ob > best) | ((ob == best) & (oi < bi));   // no branches
     best = take ? ob : best;
     bi = take ? oi : bi;
 }
@@ -114,6 +121,7 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
     const int lane = tid & 63;
 
     __shared__ double2 sh_col[2][DY_TR * RA];   // padded rows hold zeros
+    __shared__ double2 sh_f[2][DY_TR * RA];     // factors f_i of the step
     __shared__ double2 sh_row[TC * CB];         // padded columns hold zeros
     __shared__ int sh_r[2];
     __shared__ int perm[DY_MAXN], rinv[DY_MAXN];
@@ -197,7 +205,20 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 argmax_step<4>(best, bi);
                 argmax_step<2>(best, bi);
                 argmax_step<1>(best, bi);
-                if (tr == 0) sh_r[buf] = (best > 0.0 && bi < n) ? bi : -1;
+                const int rk = (best > 0.0 && bi < n) ? bi : -1;
+                // the owners form the factors once: f_i = M[i][k]/p (i != r),
+                // f_r = 1 - 1/p (singular or NaN: continue with row k)
+                const int rp = rk < 0 ? k : rk;
+                wave_sync();   // column k is in sh_col (written by this wave)
+                const double2 ip = cinv(sh_col[buf][rp]);
+#pragma unroll
+                for (int ia = 0; ia < RA; ++ia) {
+                    const int i = tr + DY_TR * ia;
+                    const double2 v = sh_col[buf][i];
+                    sh_f[buf][i] = i == rp ? make_double2(1.0 - ip.x, -ip.y)
+                                           : make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
+                }
+                if (tr == 0) sh_r[buf] = rk;
             }
             __syncthreads();
             int r = sh_r[buf];
@@ -208,9 +229,6 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
             }
             const int rr = r & (DY_TR - 1);
             const int ra = __builtin_amdgcn_readfirstlane(r >> 4);
-            // the pivot is already published with column k: invert it while the
-            // row owners publish row r
-            const double2 ipiv = cinv(sh_col[buf][r]);
             if (active && tr == rr) {
                 pivmask |= 1u << ra;
 #pragma unroll
@@ -241,13 +259,8 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 for (int jb = 0; jb < CB; ++jb) crow[jb] = sh_row[tc + TC * jb];
 #pragma unroll
                 for (int ia = 0; ia < RA; ++ia) {
-                    const int i = tr + DY_TR * ia;
-                    const double2 cv = sh_col[buf][i];
-                    double fx = cv.x * ipiv.x - cv.y * ipiv.y;
-                    double fy = cv.x * ipiv.y + cv.y * ipiv.x;
-                    const bool is_r = (i == r);
-                    fx = is_r ? 1.0 - ipiv.x : fx;
-                    fy = is_r ? -ipiv.y : fy;
+                    const double2 fv = sh_f[buf][tr + DY_TR * ia];
+                    const double fx = fv.x, fy = fv.y;
 #pragma unroll
                     for (int jb = 0; jb < CB; ++jb) {
                         mr[ia][jb] = fma(-fx, crow[jb].x, mr[ia][jb]);
@@ -324,12 +337,6 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
 // f_i = M[i][k]/p (f_r = 1 - 1/p), so the other lanes only read them.
 // Partial sums: one slot per wave (slot = workgroup * DW + wave).
 constexpr int DW = 4;
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int RA, int CB>
 __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, const int nwg) {

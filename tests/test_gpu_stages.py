@@ -162,7 +162,7 @@ def _sigma_iw_case(s, rng, scale=0.05):
     return O.sigma_tau_to_iw(Y, s.beta, s.niw)
 
 
-@pytest.mark.parametrize("n", [1, 10, 25, 26, 27, 52, 53, 100])
+@pytest.mark.parametrize("n", [1, 10, 25, 26, 27, 52, 53, 70, 90, 100, 120, 141, 160])
 def test_dyson_modes_match_oracle(torch, n):
     from paper_1405_3273_amd import _lib as L
     print(f"dyson n={n}", flush=True)
