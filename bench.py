@@ -106,7 +106,7 @@ def cpu_baseline(sysm, counts, sample_tau=3, sample_freq=512):
     G = O.green_iw(-1.0, sysm.S, F, None, sysm.beta, niw, n_idx=ns)
     _ = float(np.einsum("nij,ji->", G.real, sysm.S))
     t_dys = (time.perf_counter() - t0) / sample_freq * niw
-    solves = counts["n_eval"] + counts["n_inner"]
+    solves = counts["solves"]
     t_iter = t_sig + t_dys * solves
     return {
         "value": 1.0 / t_iter, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
@@ -127,6 +127,10 @@ def main():
     ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3",
                     help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,bf16x3",
+                    help="other Sigma precisions run through the same iterations from the same\n"
+                         "start, for the whole-iteration speedup and energy difference against\n"
+                         "the FP64 form ('' to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the workload (a kernel of known\n"
                          "traffic, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -222,7 +226,34 @@ def main():
         log(f"sigma {pr}: {dt * 1e3:.1f} ms, {sig_rates[pr]['tflops_algorithmic']:.1f} TFLOP/s")
 
     counts = {"n_inner": float(np.mean([r.n_inner for r in reps])),
-              "n_eval": float(np.mean([r.n_eval for r in reps]))}
+              "n_eval": float(np.mean([r.n_eval for r in reps])),
+              "solves": prof["dyson"][1] / steps}   # Dyson launches per iteration
+    energy_main = reps[-1].energy
+    g.close()
+
+    # the other precision forms: same start, same number of iterations
+    forms = {}
+    for pr in [p for p in args.forms.split(",") if p and p != args.prec]:
+        gf = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
+                 ntau=sysm.ntau)
+        gf.reset(mu0=float(np.mean(np.diag(sysm.h))))
+        pf = L.make_params(prec=pr, damp_Sigma=0.5)
+        for w in range(args.warmup):
+            gf.iterate(pf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(steps):
+            rf = gf.iterate(pf)
+        torch.cuda.synchronize()
+        forms[pr] = {"ms_per_step": (time.perf_counter() - t1) / steps * 1e3, "energy": rf.energy}
+        log(f"form {pr}: {forms[pr]['ms_per_step']:.0f} ms/iteration, E {rf.energy:.10f}")
+        gf.close()
+    forms[args.prec] = {"ms_per_step": elapsed / steps * 1e3, "energy": energy_main}
+    if "fp64" in forms:
+        ref = forms["fp64"]
+        for pr, f in forms.items():
+            f["speedup_vs_fp64"] = ref["ms_per_step"] / f["ms_per_step"]
+            f["energy_minus_fp64"] = f["energy"] - ref["energy"]
     line = {
         "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
@@ -235,6 +266,9 @@ def main():
         "roofline": roofline,
         "kernel_classes": classes,
         "sigma_tflops": sig_rates,
+        "precision_forms": {"iterations": args.warmup + steps, "timed": steps, "forms": forms,
+                            "note": "energy after the same iterations from the same start; "
+                                    "not a converged energy"},
         "per_step": {"n_inner": counts["n_inner"], "n_eval": counts["n_eval"],
                      "ms_sigma": float(np.mean([r.ms_sigma for r in reps])),
                      "ms_fourier": float(np.mean([r.ms_fourier for r in reps])),
@@ -244,7 +278,6 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(sysm, counts)
-    g.close()
     print(json.dumps(line), flush=True)
 
 
