@@ -6,7 +6,9 @@ the N=100 molecule-shaped workload (100 electrons, banded h, naux=400,
 beta=200, 16384 Matsubara frequencies, 512 tau points, seed 300):
 Eq. (Sigma) at every tau point, Sigma(tau) -> Sigma(i w), the inner loop
 (mu search + Dyson + Fock, Pulay-mixed density) to max|dP| < 1e-10, the
-Galitskii-Migdal energy and G(i w) -> G(tau).  Warm-up iterations include
+Galitskii-Migdal energy and G(i w) -> G(tau).  By default the mu search of
+early inner passes is inexact (--mu-tol-rel); every inner loop still ends on a
+pass that located mu to tol_N = 1e-10 electrons.  Warm-up iterations include
 the Hartree-Fock reference (iteration 0).  Inputs are resident in HBM before
 the timed region.
 
@@ -127,6 +129,10 @@ def main():
     ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3",
                     help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mu-tol-rel", type=float, default=1e-2,
+                    help="inexact mu search in early inner passes: tolerance\n"
+                         "max(tol_N, rel * max|dP| of the previous pass); each inner loop still\n"
+                         "ends on a pass that used tol_N (0 = tol_N throughout)")
     ap.add_argument("--forms", default="fp64,bf16x3",
                     help="other Sigma precisions run through the same iterations from the same\n"
                          "start, for the whole-iteration speedup and energy difference against\n"
@@ -161,7 +167,7 @@ def main():
     g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
             ntau=sysm.ntau)
     g.reset(mu0=float(np.mean(np.diag(sysm.h))))
-    prm = L.make_params(prec=args.prec, damp_Sigma=0.5)
+    prm = L.make_params(prec=args.prec, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel)
 
     for w in range(args.warmup):
         r = g.iterate(prm)
@@ -237,7 +243,7 @@ def main():
         gf = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
                  ntau=sysm.ntau)
         gf.reset(mu0=float(np.mean(np.diag(sysm.h))))
-        pf = L.make_params(prec=pr, damp_Sigma=0.5)
+        pf = L.make_params(prec=pr, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel)
         for w in range(args.warmup):
             gf.iterate(pf)
         torch.cuda.synchronize()
@@ -262,7 +268,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "sigma_arithmetic": args.prec,
                    "other_stages": "f64", "inner_tol_P": prm.tol_P, "damp_Sigma": prm.damp_Sigma,
-                   "mu_search": "secant", "mix_depth": prm.mix_depth},
+                   "mu_search": "secant", "mu_tol_N": prm.tol_N, "mu_tol_N_rel": prm.tol_N_rel,
+                   "mix_depth": prm.mix_depth},
         "roofline": roofline,
         "kernel_classes": classes,
         "sigma_tflops": sig_rates,

@@ -95,6 +95,12 @@ typedef struct {
     double damp_Sigma;   /* Sigma(tau) damping a_S in the outer loop           */
     int    mu_method;    /* GF2_MU_BISECT, GF2_MU_ILLINOIS or GF2_MU_SECANT    */
     int    prec;         /* GF2_PREC_* for Sigma(tau)                          */
+    double tol_N_rel;    /* >= 0.  0: every mu search of the inner loop uses    */
+                         /* tol_N (the paper's loop as the oracle runs it).     */
+                         /* > 0: inexact mu in early passes: pass k accepts     */
+                         /* |N - nelec| < max(tol_N, min(1e-6, tol_N_rel *      */
+                         /* max|P_out - P_in| of pass k-1)); the inner loop     */
+                         /* stops only after a pass that used tol_N.            */
 } gf2_params;
 
 /* Outer-loop state, owned by the caller (device arrays [..][n][n]). */

@@ -69,7 +69,8 @@ class gf2_params(C.Structure):
     _fields_ = [("tol_mu", C.c_double), ("tol_N", C.c_double), ("tol_P", C.c_double),
                 ("tol_E", C.c_double), ("max_inner", C.c_int), ("max_bisect", C.c_int),
                 ("mu_halfwidth", C.c_double), ("damp_P", C.c_double), ("mix_depth", C.c_int),
-                ("damp_Sigma", C.c_double), ("mu_method", C.c_int), ("prec", C.c_int)]
+                ("damp_Sigma", C.c_double), ("mu_method", C.c_int), ("prec", C.c_int),
+                ("tol_N_rel", C.c_double)]
 
 
 class gf2_state(C.Structure):
@@ -151,11 +152,11 @@ def make_dims(n, nelec, ntau, niw, beta) -> gf2_dims:
 
 def make_params(tol_mu=1e-12, tol_N=1e-10, tol_P=1e-10, tol_E=1e-11, max_inner=100,
                 max_bisect=200, mu_halfwidth=0.5, damp_P=0.3, mix_depth=8, damp_Sigma=0.0,
-                mu_method="secant", prec="fp32") -> gf2_params:
+                mu_method="secant", prec="fp32", tol_N_rel=0.0) -> gf2_params:
     mm = {"bisect": GF2_MU_BISECT, "illinois": GF2_MU_ILLINOIS, "secant": GF2_MU_SECANT}[mu_method]
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     return gf2_params(tol_mu, tol_N, tol_P, tol_E, max_inner, max_bisect, mu_halfwidth, damp_P,
-                      mix_depth, damp_Sigma, mm, pr)
+                      mix_depth, damp_Sigma, mm, pr, float(tol_N_rel))
 
 
 # ---------------------------------------------------------------------------

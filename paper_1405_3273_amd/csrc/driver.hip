@@ -58,9 +58,11 @@ struct MuSearch {
     double pending = 0.0;
     bool done = false;
     double mu = 0.0;
+    double tolN = 0.0;                // acceptance |N - nelec| < tolN (params->tol_N or looser)
 
-    void start(const gf2_params *prm, double mu0, double slope_hint) {
+    void start(const gf2_params *prm, double mu0, double slope_hint, double tol_n) {
         p = prm;
+        tolN = tol_n;
         hint = slope_hint;
         have_slope = false;
         evals = 0;
@@ -109,7 +111,7 @@ struct MuSearch {
         switch (stage) {
             case 1: {
                 fa = f;
-                if (std::fabs(fa) < p->tol_N) {
+                if (std::fabs(fa) < tolN) {
                     finish(a, 0, 0, 0, 0, false);
                     return GF2_OK;
                 }
@@ -126,7 +128,7 @@ struct MuSearch {
             }
             case 2: {
                 fb = f;
-                if (std::fabs(fb) < p->tol_N) {
+                if (std::fabs(fb) < tolN) {
                     if (a < b) finish(b, a, fa, b, fb, true);
                     else finish(b, b, fb, a, fa, true);
                     return GF2_OK;
@@ -172,7 +174,7 @@ struct MuSearch {
             }
             case 5: {
                 const double mid = pending, fm = f;
-                if (std::fabs(fm) < p->tol_N) {
+                if (std::fabs(fm) < tolN) {
                     if (fm < 0.0) finish(mid, mid, fm, hi, t_hi, true);
                     else finish(mid, lo, t_lo, mid, fm, true);
                     return GF2_OK;
@@ -211,7 +213,7 @@ static int find_mu(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, const dou
     if (d->nelec < 0 || d->nelec > 2 * c->n)
         return fail(GF2_EBRACKET, "mu search: nelec outside [0, 2n]");
     MuSearch ms;
-    ms.start(p, mu0, slope ? *slope : 0.0);
+    ms.start(p, mu0, slope ? *slope : 0.0, p->tol_N);
     while (!ms.done) {
         double f;
         GF2_TRY(particle_excess(c, d, ms.pending, F, Sig, &f));
@@ -404,7 +406,17 @@ struct InnerLoop {
     MuSearch ms;
     bool have_Pin = false;
     double mu = 0.0, slope = 0.0, trPS = 0.0, e2b = 0.0;
+    double rprev = INFINITY;   // max|P_out - P_in| of the previous pass
+    double tol_pass = 0.0;     // mu acceptance of the current pass
     int it = 0, n_inner = 0, n_eval = 0, phase = 0, want = 0;
+
+    // tol_N, or with tol_N_rel > 0 the inexact rule max(tol_N, tol_N_rel * rprev)
+    // (at most 1e-6): early passes, whose P is still far from the fixed point,
+    // locate mu less tightly; once rprev <= tol_N / tol_N_rel the rule is tol_N.
+    double pass_tolerance() const {
+        if (!(p->tol_N_rel > 0.0)) return p->tol_N;
+        return std::fmax(p->tol_N, std::fmin(1e-6, p->tol_N_rel * rprev));
+    }
 
     int density_mode() const { return Sig ? GF2_DYSON_ENERGY : GF2_DYSON_FULL; }
     // doubles of `red` that on_red reads
@@ -440,7 +452,9 @@ struct InnerLoop {
         n_inner = n_eval = 0;
         phase = 0;
         want = 0;
-        ms.start(p, mu, slope);
+        rprev = INFINITY;
+        tol_pass = pass_tolerance();
+        ms.start(p, mu, slope, tol_pass);
         return GF2_OK;
     }
     // result of the phase-0 solve at ms.pending.  That solve runs in the
@@ -481,11 +495,13 @@ struct InnerLoop {
     int on_red(const double *h) {
         const int ne = c->n * c->n;
         if (want == 1) {
-            if (h[0] < p->tol_P) {
+            // converged only when this pass located mu to tol_N
+            if (h[0] < p->tol_P && tol_pass <= p->tol_N) {
                 phase = 2;
                 want = 0;
                 return GF2_OK;
             }
+            rprev = h[0];
             // push (P_in, r = P_out - P_in), dropping the oldest beyond depth
             if ((int)pl.order.size() == pl.depth) pl.order.erase(pl.order.begin());
             const int s = pl.free_slot();
@@ -525,7 +541,8 @@ struct InnerLoop {
     int next_iteration() {
         GF2_TRY(fock_run(c, Pin, F));
         if (++it > p->max_inner) return fail(GF2_ENOCONV, "gf2_iterate: inner loop did not converge");
-        ms.start(p, mu, slope);
+        tol_pass = pass_tolerance();
+        ms.start(p, mu, slope, tol_pass);
         phase = 0;
         return GF2_OK;
     }
@@ -545,6 +562,7 @@ static int check_dims(gf2_ctx *c, const gf2_dims *d, const char *who) {
 static int check_params(const gf2_params *p, const char *who) {
     if (!p) return fail(GF2_EINVAL, std::string(who) + ": params is NULL");
     if (!(p->tol_mu > 0) || !(p->tol_N > 0) || !(p->tol_P > 0) || p->max_inner < 1 ||
+        !(p->tol_N_rel >= 0) ||
         p->max_bisect < 1 || !(p->mu_halfwidth > 0) || p->mix_depth < 1 || p->mix_depth > 32 ||
         !(p->damp_P >= 0 && p->damp_P < 1) || !(p->damp_Sigma >= 0 && p->damp_Sigma < 1) ||
         (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS &&

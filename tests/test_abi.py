@@ -38,13 +38,48 @@ def test_binding_names_match_header():
         assert callable(getattr(_lib, n))
 
 
-def test_struct_layouts_match_header_sizes():
-    """ctypes mirrors of the structs have the C sizes (ints and doubles, natural alignment)."""
+def _c_layout():
+    """sizeof and field offsets of the ABI structs as the C compiler lays them out."""
+    import subprocess
+    import tempfile
+    fields = {"gf2_dims": ["n", "nelec", "ntau", "niw", "beta"],
+              "gf2_params": [f for f, _ in _params_fields()],
+              "gf2_state": ["mu", "F", "P", "G_tau", "Sigma_tau", "iteration", "has_P", "energy"],
+              "gf2_report": ["energy", "e1b", "e2b", "dE", "dP", "mu", "n_inner", "n_eval",
+                             "ms_sigma", "ms_fourier", "ms_inner", "ms_total"]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gf2.h"', "int main(void) {"]
+    for st, fl in fields.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fl:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(src, "w") as fh:
+            fh.write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    res = {}
+    for line in out.splitlines():
+        st, key, val = line.split()
+        res[(st, key)] = int(val)
+    return res
+
+
+def _params_fields():
     from paper_1405_3273_amd import _lib
-    assert ctypes.sizeof(_lib.gf2_dims) == 4 * 4 + 8
-    assert ctypes.sizeof(_lib.gf2_params) == 4 * 8 + 2 * 4 + 8 + 8 + 4 + 4 + 8 + 4 + 4
-    assert ctypes.sizeof(_lib.gf2_state) == 8 + 4 * 8 + 4 + 4 + 8
-    assert ctypes.sizeof(_lib.gf2_report) == 6 * 8 + 2 * 4 + 4 * 8
+    return _lib.gf2_params._fields_
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the structs have the C compiler's sizes and field offsets."""
+    from paper_1405_3273_amd import _lib
+    lay = _c_layout()
+    for st in ("gf2_dims", "gf2_params", "gf2_state", "gf2_report"):
+        cls = getattr(_lib, st)
+        assert ctypes.sizeof(cls) == lay[(st, "size")], st
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == lay[(st, f)], (st, f)
 
 
 def test_last_error_is_callable_without_a_gpu():

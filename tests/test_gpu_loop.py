@@ -78,3 +78,24 @@ def test_hubbard_atom_through_the_library(torch):
     # first correlated iteration: Sigma(tau) = -U^2/8 at every tau
     assert np.max(np.abs(g.Sigma_tau.cpu().numpy() + U * U / 8.0)) < 1e-9
     g.close()
+
+
+@pytest.mark.parametrize("rel", [1e-2, 1.0])
+def test_inexact_mu_search_reaches_the_same_iterations(torch, oracle_run, rel):
+    """tol_N_rel > 0 (mu located loosely while P is far from the fixed point)
+    ends every inner loop on a pass that used tol_N, so the outer iterations
+    agree with the oracle's to the same 1e-10 relative bar."""
+    from paper_1405_3273_amd.runtime import Gf2
+    from paper_1405_3273_amd import make_params
+    s, p, reps, st = oracle_run
+    g = Gf2(s.S, s.h, s.v, nelec=s.nelec, beta=s.beta, niw=s.niw, ntau=s.ntau)
+    g.reset(mu0=-1.0)
+    prm = _params(p, "fp64")
+    prm.tol_N_rel = rel
+    for it, ref in enumerate(reps):
+        r = g.iterate(prm)
+        print(f"rel {rel} it {it}: E {r.energy:.12f} / {ref.energy:.12f} evals {r.n_eval}/{ref.n_eval} "
+              f"inner {r.n_inner}/{ref.n_inner}", flush=True)
+        assert r.energy == pytest.approx(ref.energy, rel=1e-10)
+        assert r.mu == pytest.approx(ref.mu, abs=1e-9)
+    g.close()
