@@ -148,7 +148,10 @@ int gf2_set_system(gf2_ctx *ctx, int n, const double *S, const double *h, const 
 
 /* gf2_sigma_tau: Eq. (Sigma) at every tau point, G(-tau) from
  * antiperiodicity.  G_tau: device [ntau][n][n] FP64 (symmetric).
- * Sigma_tau: device [ntau][n][n] FP64 output (may not alias G_tau).
+ * Sigma_tau: device [ntau][n][n] FP64 output (may not alias G_tau),
+ * exactly symmetric: each pair (i, j), (j, i) holds the mean of the two
+ * computed values (Sigma is symmetric for real orbitals; the mean keeps the
+ * rounding of the reduced-precision forms out of the antisymmetric part).
  * prec: GF2_PREC_*.  dims->n must equal the n of gf2_set_system;
  * nelec, niw are ignored.  Returns GF2_ENONFINITE if the result holds a
  * NaN or Inf.

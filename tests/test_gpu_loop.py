@@ -99,3 +99,41 @@ def test_inexact_mu_search_reaches_the_same_iterations(torch, oracle_run, rel):
         assert r.energy == pytest.approx(ref.energy, rel=1e-10)
         assert r.mu == pytest.approx(ref.mu, abs=1e-9)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_converged_energy(torch, prec):
+    """The loop run to self-consistency (FP64: |dE| < 1e-9 Eh and max|dP| <
+    1e-8 between outer iterations, as the stored oracle run; FP32, BF16x3:
+    1e-7 and 1e-6) and 15 iterations beyond reaches the oracle's converged
+    energy within the bar of each Sigma arithmetic."""
+    import json
+    import os
+    from paper_1405_3273_amd.runtime import Gf2
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "converged_n10.json")) as f:
+        gold = json.load(f)
+    s = small_molecule()
+    p = O.Params(damp_Sigma=gold["damp_Sigma"])
+    g = Gf2(s.S, s.h, s.v, nelec=s.nelec, beta=s.beta, niw=s.niw, ntau=s.ntau)
+    g.reset(mu0=gold["mu0"])
+    prm = _params(p, prec)
+    # the reduced-precision forms have a noise floor (FP32 ~1e-8 Eh, BF16x3 ~3e-8 Eh
+    # between outer iterations) above the FP64 thresholds
+    tE, tP = (gold["tol_dE_outer"], gold["tol_dP_outer"]) if prec == "fp64" else (1e-7, 1e-6)
+    conv = None
+    for it in range(120):
+        r = g.iterate(prm)
+        if conv is None and it > 1 and abs(r.dE) < tE and r.dP < tP:
+            conv = it + 1
+        if conv is not None and it + 1 == conv + gold["extra_iterations"]:
+            break
+    done = conv is not None
+    print(f"{prec}: converged at {conv}, E {r.energy:.12f} / {gold['energy']:.12f} "
+          f"(oracle: converged at {gold['converged_at']})", flush=True)
+    assert done
+    if prec == "fp64":
+        assert r.energy == pytest.approx(gold["energy"], rel=1e-10)
+    else:
+        assert abs(r.energy - gold["energy"]) <= E_TOL[prec]
+    g.close()
