@@ -893,6 +893,7 @@ struct S4Args {
     long long K, kz;
     int n, R, nrb, nsplit;
     int vec;            // n divisible by the vector width
+    int ncb;            // column blocks of 16 * NT columns per row block (1 or 2)
 };
 
 constexpr int S4_WAVES = 8;               // one 16-row tile per wave
@@ -911,7 +912,8 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
     constexpr int SK = BK + (F64 ? 2 : 4);
     constexpr int SB = BN + ((16 - BN % 32) + 32) % 32;
     constexpr int A_IT = BMR * 8 / S4_THREADS;        // 16-B A loads per thread
-    constexpr int B_IT = (BK * BN / VEC + S4_THREADS - 1) / S4_THREADS;
+    constexpr int BC = BN / VEC;                      // vector loads per B row
+    constexpr int B_IT = (BK * BC + S4_THREADS - 1) / S4_THREADS;
     constexpr int AROWS = S4_THREADS / 8;             // rows covered per A load round
     constexpr int FLUSH = 512 / BK;
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
@@ -921,8 +923,10 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
 
     S4Args a;
     int L;
-    if (!kresolve(ref, ref.one.nrb * ref.one.nsplit, a, L)) return;
-    const int rb = L % a.nrb, z = L / a.nrb;
+    if (!kresolve(ref, ref.one.nrb * ref.one.nsplit * ref.one.ncb, a, L)) return;
+    // rows fastest, then column blocks, then slices: the blocks of one W2 slice are adjacent
+    const int rb = L % a.nrb, cbk = (L / a.nrb) % a.ncb, z = L / (a.nrb * a.ncb);
+    const int col0 = cbk * BN;
     const int N = a.n;
     const long long k0 = (long long)z * a.kz;
     const long long kend = std::min<long long>(a.K, k0 + a.kz);
@@ -975,23 +979,26 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
             }
             ra[j] = v;
         }
-        // B chunk: rows kb .. kb + BK - 1 of W2, contiguous BK * N elements
-        const T *wb = W + (size_t)kb * N;
-        const long long nvalid = (std::min<long long>(kend, kb + BK) - kb) * N;
+        // B chunk: rows kb .. kb + BK - 1 of W2, columns col0 .. col0 + BN - 1
 #pragma unroll
         for (int j = 0; j < B_IT; ++j) {
             const int u = tid + j * S4_THREADS;
-            const long long e0 = (long long)u * VEC;
+            const int kr = u / BC, c = (u % BC) * VEC;
+            const long long gk = kb + kr;
+            const int gc = col0 + c;
+            const bool ok = u < BK * BC && gk < kend;
             vec_t v;
             if (a.vec) {
-                if (e0 < nvalid) v = *reinterpret_cast<const vec_t *>(wb + e0);
-                else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) v[e] = T(0);
-                }
+                // Clamped addresses, no value select (a select would wait for the load
+                // here): rows past the slice meet zero A columns, columns past N only
+                // reach outputs j >= N, and both read finite W2 values.
+                const long long gkc = gk < a.K ? gk : a.K - 1;
+                const int gcc = gc < N ? gc : N - VEC;
+                v = *reinterpret_cast<const vec_t *>(W + (size_t)gkc * N + gcc);
             } else {
+                const T *src = W + (size_t)gk * N + gc;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) v[e] = (e0 + e < nvalid) ? wb[e0 + e] : T(0);
+                for (int e = 0; e < VEC; ++e) v[e] = (ok && gc + e < N) ? src[e] : T(0);
             }
             rbv[j] = v;
         }
@@ -1003,19 +1010,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
 #pragma unroll
         for (int j = 0; j < B_IT; ++j) {
             const int u = tid + j * S4_THREADS;
-            const int e0 = u * VEC;
-            if (e0 < BK * N) {
-                const int kr = e0 / N, col = e0 - kr * N;
-                if (a.vec) {
-                    *reinterpret_cast<vec_t *>(&Bs[kr][col]) = rbv[j];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        const int kk = (e0 + e) / N, cl = (e0 + e) - kk * N;
-                        if (kk < BK) Bs[kk][cl] = rbv[j][e];
-                    }
-                }
-            }
+            if (u < BK * BC) *reinterpret_cast<vec_t *>(&Bs[u / BC][(u % BC) * VEC]) = rbv[j];
         }
     };
 
@@ -1058,7 +1053,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
         for (int e = 0; e < 4; ++e) {
             const int row = F64 ? ((lane >> 4) + 4 * e) : (4 * (lane >> 4) + e);
             const int m = r0 + wave * 16 + row;
-            const int j = cc * 16 + (lane & 15);
+            const int j = col0 + cc * 16 + (lane & 15);
             if (m < a.R && j < N) {
                 double val;
                 if constexpr (F64) val = acc[cc][e];
@@ -1635,6 +1630,7 @@ static int build_bf3_layouts(gf2_ctx *c) {
 struct SigShape {
     int b = 0;
     int waves = 0;
+    int s4cb = 0;   // FP64/FP32 final contraction: column blocks per row block (1 or 2)
 };
 
 struct SigPlan {
@@ -1643,6 +1639,7 @@ struct SigPlan {
     const double *G = nullptr;
     double *Sig = nullptr;
     int KT = 0, SL = 0, lq = 0, KP = 0, SLG = 0, nsplit = 0, s1_bk = 16;
+    int s4_nt = 0;   // 16-column tiles per S4 workgroup (KT split over sh.s4cb blocks)
     long long kz = 0;
     size_t t1_plane = 0, gq_plane = 0;
     SigShape sh;
@@ -1696,6 +1693,8 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
         p.sh.waves = (p.mode == MODE_F64) ? default_waves<MODE_F64>(p.KT, n)
                                           : default_waves<MODE_F32>(p.KT, n);
     }
+    p.sh.s4cb = (p.mode == MODE_BF3) ? 1 : (sh.s4cb > 0 ? std::min(sh.s4cb, 2) : 1);
+    p.s4_nt = (p.KT + p.sh.s4cb - 1) / p.sh.s4cb;
     const size_t b = (size_t)p.sh.b;
     p.t1_plane = b * N2 * N * p.lq;
     p.gq_plane = b * 16 * p.KT * p.SLG;
@@ -1810,6 +1809,7 @@ static S4Args plan_s4(const SigPlan &p, int nb) {
     a.nrb = (int)((R + S4_BM - 1) / S4_BM);
     a.nsplit = p.nsplit;
     a.vec = (p.mode == MODE_F64) ? (p.n % 2 == 0) : (p.n % 4 == 0);
+    a.ncb = p.sh.s4cb;
     return a;
 }
 
@@ -1881,9 +1881,9 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
         } else {
             KRef<S4Args> r{};
             r.one = plan_s4(p, nb);
-            const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit));
-            if (p.mode == MODE_F64) GF2_TRY(launch_s4<MODE_F64>(st, p.KT, grid, r));
-            else GF2_TRY(launch_s4<MODE_F32>(st, p.KT, grid, r));
+            const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit * r.one.ncb));
+            if (p.mode == MODE_F64) GF2_TRY(launch_s4<MODE_F64>(st, p.s4_nt, grid, r));
+            else GF2_TRY(launch_s4<MODE_F32>(st, p.s4_nt, grid, r));
         }
         if (prof) prof_end(c, ph, fl);
     }
@@ -1922,12 +1922,13 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, SigShape> g_tune;
 
 static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape &out) {
-    // GF2_SIGMA_SHAPE="b,waves" forces a shape (read on every call; for tests
+    // GF2_SIGMA_SHAPE="b,waves[,s4cb]" forces a shape (read on every call; for tests
     // of the invariance and for sweeps)
     if (const char *fs = std::getenv("GF2_SIGMA_SHAPE")) {
-        int b = 0, w = 0;
-        if (std::sscanf(fs, "%d,%d", &b, &w) == 2 && b > 0 && w > 0) {
-            out = SigShape{b, w};
+        int b = 0, w = 0, cb = 0;
+        const int got = std::sscanf(fs, "%d,%d,%d", &b, &w, &cb);
+        if (got >= 2 && b > 0 && w > 0) {
+            out = SigShape{b, w, got == 3 ? cb : 0};
             return GF2_OK;
         }
     }
@@ -1953,12 +1954,14 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
         GF2_HIP(hipEventCreate(&e1));
         double best_t = 1e300;
         int rc = GF2_OK;
+        std::vector<int> cbs = (prec == MODE_BF3) ? std::vector<int>{1} : std::vector<int>{1, 2};
         for (int b : bs) {
+          for (int cb : cbs) {
             for (int w : ws) {
                 SigPlan p;
-                rc = plan_init(c, ntau, prec, G, Sig, SigShape{b, w}, p);
+                rc = plan_init(c, ntau, prec, G, Sig, SigShape{b, w, cb}, p);
                 if (rc != GF2_OK) break;
-                if (p.sh.waves != w) continue;   // not a distinct shape for this class
+                if (p.sh.waves != w || p.sh.s4cb != cb) continue;   // not a distinct shape
                 if (prec == MODE_BF3) rc = fill_zero(c, c->sig_T1.ptr, 2 * p.t1_plane * 2);
                 if (rc != GF2_OK) break;
                 const int nb = std::min(b, ntau);
@@ -1972,10 +1975,12 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
                 const double per_tau = ms / nb;
                 if (per_tau < best_t) {
                     best_t = per_tau;
-                    best = SigShape{b, p.sh.waves};
+                    best = SigShape{b, p.sh.waves, p.sh.s4cb};
                 }
             }
             if (rc != GF2_OK) break;
+          }
+          if (rc != GF2_OK) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2039,7 +2044,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
     long long key = 1469598103934665603LL ^ prec;
     auto mix = [&](long long v) { key = (key ^ v) * 1099511628211LL; };
     for (auto &p : plans) {
-        mix(p.n); mix(p.ntau); mix(p.sh.b); mix(p.sh.waves);
+        mix(p.n); mix(p.ntau); mix(p.sh.b); mix(p.sh.waves); mix(p.sh.s4cb);
         mix((long long)(uintptr_t)p.G); mix((long long)(uintptr_t)p.Sig);
         mix((long long)(uintptr_t)p.c->sig_T1.ptr); mix((long long)(uintptr_t)p.c->sig_X.ptr);
         mix((long long)(uintptr_t)p.c->sig_part.ptr); mix((long long)(uintptr_t)p.c->sig_Gp.ptr);
@@ -2114,7 +2119,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
         }
         // S4 classes (NT)
         std::map<int, std::vector<int>> c4;
-        for (int s : act) c4[plans[s].KT].push_back(s);
+        for (int s : act) c4[prec == MODE_BF3 ? plans[s].KT : plans[s].s4_nt].push_back(s);
         for (auto &kv : c4) {
             std::vector<int> boff{0};
             GroupLaunch gl{4, kv.first, 0, 0, 0, 0, (int)kv.second.size(), 0, 0};
@@ -2129,7 +2134,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                 std::vector<S4Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s4(plans[s], nb_of(s)));
-                    boff.push_back(boff.back() + tab.back().nrb * tab.back().nsplit);
+                    boff.push_back(boff.back() + tab.back().nrb * tab.back().nsplit * tab.back().ncb);
                 }
                 push_table(buf, tab, boff, gl);
             }
