@@ -1063,10 +1063,11 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
         }
 }
 
-// Sigma_ij(tau) = Sigma_ji(tau) for real orbitals: the computed pair is replaced
-// by its mean, so no antisymmetric part (rounding of the reduced-precision
-// forms) enters the self-consistent loop.  Threads over tau x n x n; the
-// thread of (i, j), i < j, writes the pair.
+// Sigma_ij(tau) = Sigma_ji(tau) for real orbitals.  The outer loop replaces
+// each computed pair by its mean, so no antisymmetric part (rounding of the
+// reduced-precision forms) enters the self-consistent iteration; the Sigma
+// call itself returns the contraction as computed.  Threads over
+// tau x n x n; the thread of (i, j), i < j, writes the pair.
 __global__ void k_symmetrize(int n, int ntau, double *__restrict__ Sig) {
     const size_t n2 = (size_t)n * n;
     const size_t total = n2 * ntau;
@@ -1890,21 +1891,12 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
     return plan_reduce(p, st, k0, nb);
 }
 
-static int plan_symmetrize(const SigPlan &p, hipStream_t st) {
-    const size_t tot = (size_t)p.ntau * p.n * p.n;
-    if (p.n < 2) return GF2_OK;
-    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, st, p.n, p.ntau, p.Sig);
-    GF2_HIP(hipGetLastError());
-    return GF2_OK;
-}
-
 static int plan_run(SigPlan &p, bool prof) {
     if (p.mode == MODE_BF3)   // the first transform never writes the padding of the T1 rows
         GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, 2 * p.t1_plane * 2));
     for (int k0 = 0; k0 < p.ntau; k0 += p.sh.b)
         GF2_TRY(plan_run_batch(p, p.c->stream, k0, std::min(p.sh.b, p.ntau - k0), prof));
-    return plan_symmetrize(p, p.c->stream);
+    return GF2_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2218,7 +2210,6 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
             if (r * p.sh.b < p.ntau) rc = plan_reduce(p, st, r * p.sh.b, std::min(p.sh.b, p.ntau - r * p.sh.b));
         }
     }
-    for (int s = 0; s < ns && rc == GF2_OK; ++s) rc = plan_symmetrize(plans[s], st);
     const hipError_t ec = hipStreamEndCapture(st, &graph);
     if (rc != GF2_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -2232,6 +2223,16 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
     lead->sig_graph = exec;
     lead->sig_key = key;
     GF2_HIP(hipGraphLaunch(exec, lead->stream));
+    return GF2_OK;
+}
+
+int sigma_symmetrize(gf2_ctx *c, int ntau, double *Sig) {
+    const int n = c->n;
+    if (n < 2) return GF2_OK;
+    const size_t tot = (size_t)ntau * n * n;
+    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, c->stream, n, ntau, Sig);
+    GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
