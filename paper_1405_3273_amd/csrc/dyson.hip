@@ -102,6 +102,13 @@ template <int K> __device__ __forceinline__ double ror16(double v) {
     const int hi = ror16<K>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// value of v in lane `lane` (wave-uniform index) as a scalar
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 template <int K> __device__ __forceinline__ void argmax_step(double &best, int &bi) {
     const double ob = ror16<K>(best);
     const int oi = ror16<K>(bi);
@@ -120,7 +127,6 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
     const bool active = tc < TC;
     const int lane = tid & 63;
 
-    __shared__ double2 sh_col[2][DY_TR * RA];   // padded rows hold zeros
     __shared__ double2 sh_f[2][DY_TR * RA];     // factors f_i of the step
     __shared__ double2 sh_row[TC * CB];         // padded columns hold zeros
     __shared__ int sh_r[2];
@@ -181,44 +187,54 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
             const int kc = k % TC;
             const int cb = __builtin_amdgcn_readfirstlane(k / TC);
             if (active && tc == kc) {
-                double best = -1.0;
-                int bi = n;
 #pragma unroll
                 for (int jb = 0; jb < CB; ++jb) {
                     if (jb == cb) {   // scalar branch: cb is wave-uniform
+                        double best = -1.0;
+                        int bi = n;
+#pragma unroll
+                        for (int ia = 0; ia < RA; ++ia) {
+                            const int i = tr + DY_TR * ia;
+                            const double mag = fabs(mr[ia][jb]) + fabs(mi[ia][jb]);
+                            const bool cand = !((pivmask >> ia) & 1u) & (mag > best);
+                            best = cand ? mag : best;
+                            bi = cand ? i : bi;
+                        }
+                        // argmax over the 16 owners (one DPP row of 16 lanes); ties -> smaller row
+                        argmax_step<8>(best, bi);
+                        argmax_step<4>(best, bi);
+                        argmax_step<2>(best, bi);
+                        argmax_step<1>(best, bi);
+                        const int rk = (best > 0.0 && bi < n) ? bi : -1;
+                        // pivot row (singular or NaN: continue with row k); the pivot
+                        // value comes from its owner lane (wave-uniform lane index)
+                        const int rp = __builtin_amdgcn_readfirstlane(rk < 0 ? k : rk);
+                        const int src = 16 * (kc & 3) + (rp & (DY_TR - 1));
+                        const int pa = rp >> 4;
+                        double pvr = 0.0, pvi = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < RA; ++ia) {
+                            if (ia == pa) {   // scalar branch
+                                pvr = readlane_d(mr[ia][jb], src);
+                                pvi = readlane_d(mi[ia][jb], src);
+                            }
+                        }
+                        const double2 ip = cinv(make_double2(pvr, pvi));
+                        // the owners form the factors once: f_i = M[i][k]/p (i != r),
+                        // f_r = 1 - 1/p; then column k is preset to 0 (row r gets 1
+                        // when it is published)
 #pragma unroll
                         for (int ia = 0; ia < RA; ++ia) {
                             const int i = tr + DY_TR * ia;
                             const double vr = mr[ia][jb], vi = mi[ia][jb];
-                            sh_col[buf][i] = make_double2(vr, vi);
-                            const double mag = fabs(vr) + fabs(vi);
-                            const bool cand = !((pivmask >> ia) & 1u) && mag > best;
-                            best = cand ? mag : best;
-                            bi = cand ? i : bi;
-                            mr[ia][jb] = 0.0;   // preset column k (row r gets 1 below)
+                            sh_f[buf][i] = i == rp ? make_double2(1.0 - ip.x, -ip.y)
+                                                   : make_double2(vr * ip.x - vi * ip.y, vr * ip.y + vi * ip.x);
+                            mr[ia][jb] = 0.0;
                             mi[ia][jb] = 0.0;
                         }
+                        if (tr == 0) sh_r[buf] = rk;
                     }
                 }
-                // argmax over the 16 owners (one DPP row of 16 lanes); ties -> smaller row
-                argmax_step<8>(best, bi);
-                argmax_step<4>(best, bi);
-                argmax_step<2>(best, bi);
-                argmax_step<1>(best, bi);
-                const int rk = (best > 0.0 && bi < n) ? bi : -1;
-                // the owners form the factors once: f_i = M[i][k]/p (i != r),
-                // f_r = 1 - 1/p (singular or NaN: continue with row k)
-                const int rp = rk < 0 ? k : rk;
-                wave_sync();   // column k is in sh_col (written by this wave)
-                const double2 ip = cinv(sh_col[buf][rp]);
-#pragma unroll
-                for (int ia = 0; ia < RA; ++ia) {
-                    const int i = tr + DY_TR * ia;
-                    const double2 v = sh_col[buf][i];
-                    sh_f[buf][i] = i == rp ? make_double2(1.0 - ip.x, -ip.y)
-                                           : make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
-                }
-                if (tr == 0) sh_r[buf] = rk;
             }
             __syncthreads();
             int r = sh_r[buf];
