@@ -614,11 +614,12 @@ __global__ void k_stage_g(int n, int M, int k0, int nb, const double *__restrict
 }
 
 // Operand copy of G(tau) for the third transform: Gp[t][l][col], l < 16*KT,
-// col < SL, zero outside l, k < n.  Column col holds k = col, except in the
-// FP64 form, where within each 16-block col = 4a + b holds k = a + 4b (the
-// order in which an FP64 MFMA result tile hands out its rows).
-template <class T, bool PERM>
-__global__ void k_stage_gp(int n, int kt_tiles, int sl, int M, int k0, int nb,
+// col < SL, zero outside l, k < n.  Column col holds k = col below perm_from;
+// from there on, within each 16-block, col = 4a + b holds k = a + 4b: the
+// order in which the FP64 MFMA result tile hands out its rows (perm_from = 0),
+// and the order the FP32 form gives the rows of its last k tile (see k_s23).
+template <class T>
+__global__ void k_stage_gp(int n, int kt_tiles, int sl, int perm_from, int M, int k0, int nb,
                            const double *__restrict__ Gt, T *__restrict__ Gp) {
     const int p16 = 16 * kt_tiles;
     const size_t per = (size_t)p16 * sl;
@@ -629,8 +630,7 @@ __global__ void k_stage_gp(int n, int kt_tiles, int sl, int M, int k0, int nb,
         const size_t t = idx / per;
         const int rem = (int)(idx % per);
         const int l = rem / sl, col = rem % sl;
-        int k = col;
-        if (PERM) k = (col & ~15) + ((col & 15) >> 2) + 4 * (col & 3);
+        const int k = col < perm_from ? col : (col & ~15) + ((col & 15) >> 2) + 4 * (col & 3);
         double val = 0.0;
         if (col < p16 && l < n && k < n) val = Gt[(size_t)(k0 + t) * n2 + (size_t)l * n + k];
         Gp[idx] = (T)val;
@@ -649,7 +649,11 @@ __global__ void k_stage_gp(int n, int kt_tiles, int sl, int M, int k0, int nb,
 // product.  That works because an MFMA result tile holds, per lane, the rows
 // of one K group of the next product's B operand (rows 4a..4a+3 for FP32,
 // a, a+4, a+8, a+12 for FP64, a = lane/16); the A operand (G) is read in the
-// matching row order.  Workgroup = (t, n, p tile); its waves take the slabs
+// matching row order.  In its last k tile the FP32 form loads the first
+// product's A rows in the order m = 4a + b <-> k = a + 4b, so that there, as
+// in every FP64 tile, the e-th result register carries k = 4e + a: the second
+// product's e-th MFMA of the last tile contracts k = 16 (KT - 1) + 4e ..
+// + 4e + 3 and is skipped when all of them are >= N (N % 16 in 1..12).  Workgroup = (t, n, p tile); its waves take the slabs
 // i = w, w + nw, ...; G(tau) sits in LDS (or is read from the staged copy
 // when it does not fit), the p-tile columns of G(-tau) too.
 //
@@ -744,7 +748,12 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     // The slab is symmetric (v_imqk = v_imkq), so T1[q][k] is read as
     // T1[k][q]: in the grouped q order a lane's 4 consecutive q of row k are
     // one 16-B load.
-    const int kc_last = min(16 * (KT - 1) + c, N - 1);
+    // first-product A row c of the last k tile holds k = 16 (KT - 1) + kperm
+    // (see above; the FP32 form keeps k = 16 kt + c in the other tiles)
+    const int kperm = (MODE == MODE_F64) ? c : 4 * (c & 3) + (c >> 2);
+    const int kc_last = min(16 * (KT - 1) + kperm, N - 1);
+    // MFMAs of the second product's last k tile that meet some k < N
+    const int elast = __builtin_amdgcn_readfirstlane((N - 16 * (KT - 1) + 3) >> 2);
     auto slab_of = [&](int i) { return T1 + (((size_t)i * a.nb + t) * N + nn) * N2; };
     typedef T qv_t __attribute__((ext_vector_type(GW)));
     qv_t ga_[KT];                               // grouped operands (GW steps each)
@@ -836,24 +845,33 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
             // two accumulation chains (even / odd k tiles), added at the end
             acc_t acc2 = acc_t{0, 0, 0, 0}, acc2b = acc_t{0, 0, 0, 0};
             const T *grow = Gop + (16 * lt + c) * SL + 4 * g;
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt) {
-                acc_t &ac = (kt & 1) ? acc2b : acc2;
+            // e-th MFMA of tile kt: k = 16 kt + 4e + a.  The last tile goes
+            // first and runs only its MFMAs with e < elast.
+            auto ktile = [&](acc_t &ac, int kt, bool last) {
                 if constexpr (MODE == MODE_F64) {
                     const double2 g0 = *reinterpret_cast<const double2 *>(grow + 16 * kt);
                     const double2 g1 = *reinterpret_cast<const double2 *>(grow + 16 * kt + 2);
                     ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.x, acc1[kt][0], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], ac, 0, 0, 0);
+                    if (!last || elast > 1)
+                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], ac, 0, 0, 0);
+                    if (!last || elast > 2)
+                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], ac, 0, 0, 0);
+                    if (!last || elast > 3)
+                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], ac, 0, 0, 0);
                 } else {
                     const float4 gv = *reinterpret_cast<const float4 *>(grow + 16 * kt);
                     ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, acc1[kt][0], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], ac, 0, 0, 0);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], ac, 0, 0, 0);
+                    if (!last || elast > 1)
+                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], ac, 0, 0, 0);
+                    if (!last || elast > 2)
+                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], ac, 0, 0, 0);
+                    if (!last || elast > 3)
+                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], ac, 0, 0, 0);
                 }
-            }
+            };
+            ktile(((KT - 1) & 1) ? acc2b : acc2, KT - 1, true);
+#pragma unroll
+            for (int kt = 0; kt < KT - 1; ++kt) ktile((kt & 1) ? acc2b : acc2, kt, false);
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc2[e] += acc2b[e];
             if (p < N) {
@@ -1724,14 +1742,14 @@ static int plan_stage(const SigPlan &p, hipStream_t st, int k0, int nb) {
     if (p.mode == MODE_F64) {
         hipLaunchKernelGGL(k_stage_g<double>, dim3(blocks), dim3(256), 0, st, n, p.M, k0, nb, p.G,
                            c->sig_G.as<double>(), c->sig_Gb.as<double>());
-        hipLaunchKernelGGL((k_stage_gp<double, true>), dim3(blocksp), dim3(256), 0, st, n, p.KT, p.SL,
+        hipLaunchKernelGGL(k_stage_gp<double>, dim3(blocksp), dim3(256), 0, st, n, p.KT, p.SL, 0,
                            p.M, k0, nb, p.G, c->sig_Gp.as<double>());
     } else {
         hipLaunchKernelGGL(k_stage_g<float>, dim3(blocks), dim3(256), 0, st, n, p.M, k0, nb, p.G,
                            c->sig_G.as<float>(), c->sig_Gb.as<float>());
         if (p.mode == MODE_F32) {
-            hipLaunchKernelGGL((k_stage_gp<float, false>), dim3(blocksp), dim3(256), 0, st, n, p.KT,
-                               p.SL, p.M, k0, nb, p.G, c->sig_Gp.as<float>());
+            hipLaunchKernelGGL(k_stage_gp<float>, dim3(blocksp), dim3(256), 0, st, n, p.KT,
+                               p.SL, 16 * (p.KT - 1), p.M, k0, nb, p.G, c->sig_Gp.as<float>());
         } else {
             const size_t totq = (size_t)nb * 16 * p.KT * p.SLG;
             const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
