@@ -15,6 +15,7 @@ Every function cites the passage of the paper it follows:
 * Eq. (FockMatrix)  -- Fock matrix from the density (Implementation).
 * Eq. (Sigma)       -- second-order self-energy in imaginary time.
 * Eq. (GF)          -- Dyson equation on the Matsubara axis.
+* natural occupation numbers of the correlated density (Results).
 * Supplementary Material, "Implementation of GF2 algorithm", steps 1-3.
 
 Where the paper is silent (energy formula, transform quadrature, grid
@@ -34,6 +35,7 @@ from .dyson import (tail_moments, green_iw, density_from_giw, particle_number, f
 from .fock import fock
 from .energy import e_one_body, e_two_body, trigamma
 from .loop import Params, State, OuterReport, inner_loop, outer_iteration, run, pulay_mix
+from .occupations import natural_occupations
 
 __all__ = [
     "tau_grid", "matsubara",
@@ -44,4 +46,5 @@ __all__ = [
     "BracketError", "NoConvergence",
     "fock", "e_one_body", "e_two_body", "trigamma",
     "Params", "State", "OuterReport", "inner_loop", "outer_iteration", "run", "pulay_mix",
+    "natural_occupations",
 ]
