@@ -195,8 +195,9 @@ def main():
     kind = {"sigma_gemm": ("mfma", args.prec), "sigma_splitk": ("mfma", args.prec),
             "sigma_s23": ("mfma", args.prec),
             "dyson": ("alu", "fp64_vector"), "t2i_expand": ("hbm", "hbm"),
-            "i2t_fold": ("hbm", "hbm"), "fock": ("hbm", "hbm")}
-    dom = max(prof, key=lambda k: prof[k][0])
+            "i2t_fold": ("hbm", "hbm"), "fock": ("hbm", "hbm"),
+            "occupations": ("latency", None)}
+    dom = max((k for k in prof if kind[k][0] != "latency"), key=lambda k: prof[k][0])
     ms, cnt, work = prof[dom]
     bound, pk = kind[dom]
     avg_s = ms / cnt / 1e3
@@ -216,7 +217,23 @@ def main():
                    "rate": (v[2] / (v[0] / 1e3) / (1e9 if kind[k][0] == "hbm" else 1e12))
                    if v[0] > 0 else None,
                    "rate_unit": "GB/s" if kind[k][0] == "hbm" else "TFLOP/s"}
-               for k, v in prof.items()}
+               for k, v in prof.items() if kind[k][0] != "latency"}
+
+    # natural occupation numbers of the last density (not part of an iteration)
+    occ = g.natural_occupations(g.P)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nrep = 5
+    for _ in range(nrep):
+        occ = g.natural_occupations(g.P)
+    torch.cuda.synchronize()
+    occ_ms = (time.perf_counter() - t1) / nrep * 1e3
+    occ_h = occ.cpu().numpy()
+    nons = {"ms": occ_ms, "n": int(g.n), "largest": float(occ_h[0]), "smallest": float(occ_h[-1]),
+            "sum": float(occ_h.sum()),
+            "fractional": int(np.sum((occ_h > 0.02) & (occ_h < 1.98)))}
+    log(f"natural occupations: {occ_ms:.2f} ms, sum {nons['sum']:.10f}, "
+        f"{nons['fractional']} in (0.02, 1.98)")
 
     # stand-alone Sigma(tau) per precision on the current G(tau)
     sig_rates = {}
@@ -273,6 +290,7 @@ def main():
         "roofline": roofline,
         "kernel_classes": classes,
         "sigma_tflops": sig_rates,
+        "natural_occupations": nons,
         "precision_forms": {"iterations": args.warmup + steps, "timed": steps, "forms": forms,
                             "note": "energy after the same iterations from the same start; "
                                     "not a converged energy"},

@@ -198,6 +198,23 @@ int gf2_dyson(gf2_ctx *ctx, const gf2_dims *dims, int mode, double mu,
  */
 int gf2_fock(gf2_ctx *ctx, const double *P, double *F);
 
+/* gf2_natural_occupations: the natural occupation numbers of a density
+ * (Results: the NONs of the self-consistent density, plotted for the H32
+ * lattice against the lattice parameter; Supplementary Material, NON plots).
+ * The paper gives no formula; they are taken as the eigenvalues of the
+ * spin-summed density in the symmetrically orthonormalised basis,
+ * S^{1/2} P S^{1/2} (the spectrum of P S), with S of gf2_set_system.
+ * P: device [n][n] FP64, symmetric (only the whole matrix is read; it is not
+ * modified).  occ: device [n] FP64, written largest first; with tr(P S) = N_e
+ * the values lie in [0, 2] and sum to N_e.  Runs on the context's stream and
+ * synchronises it (the status of the eigensolver is read back).
+ * Errors: GF2_EINVAL for NULL arguments, n > 1024 or an overlap that is not
+ * positive definite; GF2_ESTATE without a system; GF2_ENOCONV if the Jacobi
+ * sweeps do not converge; GF2_ENONFINITE for a NaN/Inf eigenvalue (occ is
+ * written in every case except GF2_EINVAL/GF2_ESTATE).
+ */
+int gf2_natural_occupations(gf2_ctx *ctx, const double *P, double *occ);
+
 /* gf2_density_fock: one pass of steps 2.a-2.b at fixed Sigma: find mu
  * (bracketing search on tr(P(mu) S) = nelec, see gf2_params) starting from
  * *mu_inout (host), then P_out = P(mu) (device [n][n]), F_out = F(P_out)
@@ -265,6 +282,8 @@ int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
  *   GF2_KC_T2I_EXPAND    Sigma(i w) expansion;                 work = bytes written (16 n^2 niw)
  *   GF2_KC_I2T_FOLD      G(i w) fold;                          work = bytes read (16 n^2 niw)
  *   GF2_KC_FOCK          Eq. (FockMatrix);                     work = bytes read (8 n^4)
+ *   GF2_KC_OCCUPATIONS   natural occupation numbers (gf2_natural_occupations, all
+ *                        three steps as one bracket);          work = n (eigenvalues)
  * gf2_profile_enable(ctx, 1) clears the counters and starts recording;
  * gf2_profile_enable(ctx, 0) stops.  gf2_profile_read synchronises the
  * stream and fills host arrays [nslots] (nslots <= GF2_KC_COUNT) with the
@@ -277,7 +296,8 @@ int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
 #define GF2_KC_I2T_FOLD     4
 #define GF2_KC_FOCK         5
 #define GF2_KC_SIGMA_S23    6
-#define GF2_KC_COUNT        7
+#define GF2_KC_OCCUPATIONS  7
+#define GF2_KC_COUNT        8
 
 int gf2_profile_enable(gf2_ctx *ctx, int on);
 int gf2_profile_read(gf2_ctx *ctx, int nslots, double *ms, long long *launches, double *work);

@@ -40,7 +40,8 @@ GF2_MU_SECANT = 2
 
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
-            "gf2_iterate", "gf2_iterate_batched", "gf2_profile_enable", "gf2_profile_read")
+            "gf2_iterate", "gf2_iterate_batched", "gf2_natural_occupations",
+            "gf2_profile_enable", "gf2_profile_read")
 
 GF2_KC_SIGMA_GEMM = 0
 GF2_KC_SIGMA_SPLITK = 1
@@ -49,9 +50,10 @@ GF2_KC_T2I_EXPAND = 3
 GF2_KC_I2T_FOLD = 4
 GF2_KC_FOCK = 5
 GF2_KC_SIGMA_S23 = 6
-GF2_KC_COUNT = 7
+GF2_KC_OCCUPATIONS = 7
+GF2_KC_COUNT = 8
 KERNEL_CLASSES = ("sigma_gemm", "sigma_splitk", "dyson", "t2i_expand", "i2t_fold", "fock",
-                  "sigma_s23")
+                  "sigma_s23", "occupations")
 
 
 class Gf2Error(RuntimeError):
@@ -111,6 +113,7 @@ def load(path: str = None):
         "gf2_fourier": ([vp, C.POINTER(gf2_dims), i, vp, vp, vp, vp], i),
         "gf2_dyson": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
         "gf2_fock": ([vp, vp, vp], i),
+        "gf2_natural_occupations": ([vp, vp, vp], i),
         "gf2_density_fock": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), vp, vp, vp, dp, vp,
                               vp, vp, dp], i),
         "gf2_iterate": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), C.POINTER(gf2_state),
@@ -202,6 +205,10 @@ def gf2_dyson(ctx, dims: gf2_dims, mode, mu, F, Sigma_iw=None, Sigma1=None, G_iw
 
 def gf2_fock(ctx, P, F):
     _check(load().gf2_fock(ctx, _ptr(P), _ptr(F)))
+
+
+def gf2_natural_occupations(ctx, P, occ):
+    _check(load().gf2_natural_occupations(ctx, _ptr(P), _ptr(occ)))
 
 
 def gf2_density_fock(ctx, dims: gf2_dims, params: gf2_params, F_in, Sigma_iw, Sigma1, mu,

@@ -81,6 +81,7 @@ struct gf2_ctx {
     gf2::DevBuf four_c, four_C, four_fold, four_twid;
     gf2::DevBuf dys_part, dys_X, dys_aux, dys_out;
     gf2::DevBuf fock_part;
+    gf2::DevBuf occ_ws;                   // natural occupations: L, L^T, P L, A, status
     gf2::DevBuf it_Sig_iw, it_G_iw, it_Sig1, it_mom, it_Sig_new, it_Pout, it_Pin, it_F, it_tmp;
     gf2::DevBuf it_hist;                  // Pulay history on the device: [2*depth][n][n]
     gf2::DevBuf it_red;                   // inner-loop reduction results

@@ -83,6 +83,12 @@ class Gf2:
         L.gf2_fock(self.ctx, P, F)
         return F
 
+    def natural_occupations(self, P):
+        """Natural occupation numbers of the density P, largest first."""
+        occ = self._empty(self.n)
+        L.gf2_natural_occupations(self.ctx, P, occ)
+        return occ
+
     def density_fock(self, params, F_in, mu, Sigma_iw=None, Sigma1=None, want_G=False):
         P = self._empty(self.n, self.n)
         F = self._empty(self.n, self.n)
