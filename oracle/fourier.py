@@ -4,7 +4,10 @@ Conventions (the paper fixes none of them; these are the readings):
 
 * G(i omega_n) = int_0^beta exp(i omega_n tau) G(tau) dtau,
   G(tau) = (1/beta) sum_{n in Z} exp(-i omega_n tau) G(i omega_n).
-* Uniform grid tau_k = k beta/M (see ``grids``).
+* Uniform grid tau_k = k beta/M (see ``grids``), or any strictly increasing
+  grid tau_0 = 0 < ... < tau_M = beta passed as ``tau`` (the paper uses a
+  non-equidistant grid, Implementation section).  Only the 'direct' sums
+  apply to a non-uniform grid.
 
 Sigma(tau) -> Sigma(i omega) (step 3 of the Supplementary Material).  The
 paper says only that an FFT is used.  Reading: interpolate every matrix
@@ -47,14 +50,15 @@ def _phase(num: np.ndarray, M: int) -> np.ndarray:
     return np.exp(1j * np.pi * r / M)
 
 
-def spline_coefficients(Y: np.ndarray, beta: float) -> np.ndarray:
-    """Not-a-knot cubic spline of Y[k] over the uniform tau grid (axis 0).
+def spline_coefficients(Y: np.ndarray, beta: float, tau=None) -> np.ndarray:
+    """Not-a-knot cubic spline of Y[k] over the tau grid (axis 0; uniform
+    when ``tau`` is None).
 
     Returns c[k][j] (k = 0..3): the spline on [tau_j, tau_{j+1}] is
     sum_k c[k][j] (tau - tau_j)^k.
     """
     ntau = Y.shape[0]
-    tau = tau_grid(beta, ntau)
+    tau = tau_grid(beta, ntau) if tau is None else np.asarray(tau, dtype=np.float64)
     spl = CubicSpline(tau, Y, axis=0, bc_type="not-a-knot")
     return spl.c[::-1]            # scipy stores the highest power first
 
@@ -84,18 +88,39 @@ def moments_unit(theta: np.ndarray, kmax: int = 3) -> np.ndarray:
     return out
 
 
+def _phase_grid(n_odd: np.ndarray, tau: np.ndarray, beta: float) -> np.ndarray:
+    """exp(i pi n_odd tau / beta) for a general grid, the argument reduced mod 2."""
+    x = np.mod(np.multiply.outer(n_odd.astype(np.float64), tau / beta), 2.0)
+    return np.exp(1j * np.pi * x)
+
+
 def sigma_tau_to_iw(Sig_tau: np.ndarray, beta: float, niw: int, n_idx=None,
-                    method: str = "fft"):
+                    method: str = "fft", tau=None):
     """Sigma(tau) [ntau][n][n] -> (Sigma(i omega_n) [len][n][n] complex, Sigma_1).
 
     ``method='direct'`` sums over the intervals term by term for the
     requested frequencies (the definition); ``'fft'`` evaluates the four
-    M-periodic sums over intervals with length-M FFTs.
+    M-periodic sums over intervals with length-M FFTs (uniform grid only).
+    With a grid ``tau`` the interval widths h_j = tau_{j+1} - tau_j enter
+    each term: Sigma(i w_n) = sum_j exp(i w_n tau_j) sum_k c_kj h_j^{k+1}
+    mu_k(w_n h_j).
     """
     ntau = Sig_tau.shape[0]
     M = ntau - 1
-    h = beta / M
     ns = np.arange(niw) if n_idx is None else np.asarray(n_idx)
+    if tau is not None:
+        tau = np.asarray(tau, dtype=np.float64)
+        if tau.shape != (ntau,):
+            raise ValueError("tau grid length differs from Sig_tau")
+        c = spline_coefficients(Sig_tau, beta, tau)        # [4][M][n][n]
+        hj = np.diff(tau)
+        w = np.pi * (2 * ns + 1) / beta
+        mom = moments_unit(np.multiply.outer(w, hj))       # [4][len][M]
+        ph = _phase_grid(2 * ns + 1, tau[:-1], beta)       # [len][M]
+        Sig_iw = sum(np.tensordot(ph * mom[k] * hj[None, :] ** (k + 1), c[k], axes=([1], [0]))
+                     for k in range(4))
+        return Sig_iw, -(Sig_tau[0] + Sig_tau[-1])
+    h = beta / M
     c = spline_coefficients(Sig_tau, beta)                 # [4][M][n][n]
     mom = moments_unit(np.pi * (2 * ns + 1) / M)           # mu_k(w_n h), [4][len]
     j = np.arange(M)
@@ -120,8 +145,9 @@ def tail_tau(tau, G1, G2, G3, beta):
 
 
 def g_iw_to_tau(G_iw: np.ndarray, G1, G2, G3, beta: float, ntau: int, k_idx=None,
-                method: str = "fft") -> np.ndarray:
-    """G(i omega_n), n = 0..niw-1 -> G(tau_k) on the uniform grid.
+                method: str = "fft", tau=None) -> np.ndarray:
+    """G(i omega_n), n = 0..niw-1 -> G(tau_k) on the tau grid (uniform when
+    ``tau`` is None; a grid ``tau`` takes the direct sum).
 
     G(tau) = (2/beta) Re sum_{n<niw} exp(-i w_n tau) [G - tail](i w_n) + tail(tau).
     """
@@ -130,6 +156,11 @@ def g_iw_to_tau(G_iw: np.ndarray, G1, G2, G3, beta: float, ntau: int, k_idx=None
     ks = np.arange(ntau) if k_idx is None else np.asarray(k_idx)
     iw = 1j * matsubara(beta, niw)[:, None, None]
     R = G_iw - G1 / iw - G2 / iw ** 2 - G3 / iw ** 3
+    if tau is not None:
+        tk = np.asarray(tau, dtype=np.float64)[ks]
+        ph = np.conj(_phase_grid(2 * np.arange(niw) + 1, tk, beta)).T   # [k][n]
+        S = np.tensordot(ph, R, axes=([1], [0]))
+        return (2.0 / beta) * S.real + tail_tau(tk, G1, G2, G3, beta)
     if method == "direct":
         ph = _phase(-np.outer(ks, 2 * np.arange(niw) + 1), M)   # exp(-i w_n tau_k)
         S = np.tensordot(ph, R, axes=([1], [0]))

@@ -180,6 +180,11 @@ def inner_loop(sysm, params: Params, F, P_in, mu0, Sigma_iw, Sigma1):
     raise NoConvergence("inner loop did not converge")
 
 
+def _method(sysm) -> str:
+    """The FFT form for a uniform grid, the defining sum for a given grid."""
+    return "direct" if getattr(sysm, "tau", None) is not None else "fft"
+
+
 def outer_iteration(sysm, params: Params, st: State) -> OuterReport:
     """One outer iteration.  Iteration 0 is the finite-beta HF reference."""
     n = sysm.n
@@ -192,14 +197,15 @@ def outer_iteration(sysm, params: Params, st: State) -> OuterReport:
         Sig_tau = sigma_tau(st.G_tau, sysm.v)
         if st.iteration >= 2 and params.damp_Sigma > 0.0:
             Sig_tau = (1.0 - params.damp_Sigma) * Sig_tau + params.damp_Sigma * st.Sigma_tau
-        Sigma_iw, Sigma1 = sigma_tau_to_iw(Sig_tau, beta, niw)
+        Sigma_iw, Sigma1 = sigma_tau_to_iw(Sig_tau, beta, niw, method=_method(sysm),
+                                           tau=getattr(sysm, "tau", None))
     P_prev = st.P
     mu, P, F, G, mom, n_inner, n_eval = inner_loop(
         sysm, params, st.F, st.P, st.mu, Sigma_iw, Sigma1)
     e1 = e_one_body(P, sysm.h, F)
     e2 = 0.0 if Sigma_iw is None else e_two_body(G, Sigma_iw, mom[0], Sigma1, beta)
     E = e1 + e2
-    G_tau = g_iw_to_tau(G, *mom, beta, ntau)
+    G_tau = g_iw_to_tau(G, *mom, beta, ntau, tau=getattr(sysm, "tau", None))
     dE = E - st.energy if np.isfinite(st.energy) else float("inf")
     dP = float(np.max(np.abs(P - P_prev))) if P_prev is not None else float("inf")
     st.mu, st.F, st.P, st.G_tau, st.Sigma_tau = mu, F, P, G_tau, Sig_tau

@@ -38,7 +38,9 @@ def bracket_W(v: np.ndarray) -> np.ndarray:
 
 
 def gbar_from_gtau(G_tau: np.ndarray) -> np.ndarray:
-    """G(-tau_k) = -G(tau_{M-k}) on the uniform grid (antiperiodicity)."""
+    """G(-tau_k) = -G(tau_{M-k}) (antiperiodicity), on any grid symmetric
+    about beta/2 (tau_{M-k} = beta - tau_k): the uniform grid and the
+    power grid of the inputs."""
     return -G_tau[::-1]
 
 

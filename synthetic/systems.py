@@ -47,6 +47,7 @@ class System:
     ntau: int              # imaginary-time points incl. both endpoints
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    tau: Optional[np.ndarray] = None   # non-uniform tau grid (ntau points), None = uniform
 
     @property
     def n(self) -> int:
@@ -216,3 +217,26 @@ def random_tau_stack(rng: np.random.Generator, ntau: int, n: int, scale: float =
     """[ntau][n][n] stack of random symmetric matrices."""
     X = rng.standard_normal((ntau, n, n)) * scale
     return 0.5 * (X + X.transpose(0, 2, 1))
+
+
+def power_tau_grid(beta: float, levels: int, per_level: int) -> np.ndarray:
+    """Non-equidistant tau grid, dense at both ends and symmetric about beta/2.
+
+    On [0, beta/2] the nodes x_l = (beta/2) 2^-l (l = 0..levels-1) and 0 cut
+    the half interval into `levels` pieces, each split into `per_level`
+    equal steps; the other half is the mirror image tau -> beta - tau.
+    2 levels per_level + 1 points, tau_0 = 0, tau_M = beta, and
+    tau_{M-k} = beta - tau_k (so G(-tau_k) = -G(tau_{M-k}) stays on the grid).
+    """
+    if levels < 1 or per_level < 1 or 2 * levels * per_level < 3:
+        raise ValueError("power_tau_grid: needs levels, per_level >= 1 and at least 4 points")
+    half = 0.5 * beta
+    edges = [0.0] + [half * 2.0 ** (-l) for l in range(levels - 1, -1, -1)]
+    pts = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        pts.extend(a + (b - a) * np.arange(per_level) / per_level)
+    left = np.array(pts + [half])
+    right = beta - left[-2::-1]
+    tau = np.concatenate([left, right])
+    tau[0], tau[-1] = 0.0, beta
+    return tau

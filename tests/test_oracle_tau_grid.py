@@ -1,0 +1,69 @@
+"""Pins for the oracle's transforms on a non-equidistant tau grid (the
+paper's choice, Implementation section): the grid form equals the uniform
+form on a uniform grid, integrates a cubic exactly (closed form by parts),
+and G(i w) -> G(tau) reproduces the closed-form Hartree-Fock G(tau) at the
+grid points."""
+import numpy as np
+
+import oracle as O
+from oracle import reference as R
+from oracle.grids import tau_grid, matsubara
+from synthetic import generic_system, power_tau_grid
+
+
+def test_power_grid_is_symmetric_and_dense_at_the_ends():
+    tau = power_tau_grid(200.0, 8, 32)
+    assert tau.shape == (513,) and tau[0] == 0.0 and tau[-1] == 200.0
+    np.testing.assert_allclose(tau + tau[::-1], 200.0, rtol=0, atol=1e-12)
+    h = np.diff(tau)
+    assert np.all(h > 0) and h[0] < h[256] / 32
+
+
+def test_grid_form_equals_uniform_form_on_a_uniform_grid():
+    rng = np.random.default_rng(2)
+    beta, ntau, niw, n = 12.0, 33, 300, 3
+    Y = rng.standard_normal((ntau, n, n))
+    ref, s1 = O.sigma_tau_to_iw(Y, beta, niw, method="direct")
+    got, s1g = O.sigma_tau_to_iw(Y, beta, niw, tau=tau_grid(beta, ntau))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_array_equal(s1g, s1)
+    G = rng.standard_normal((niw, n, n)) + 1j * rng.standard_normal((niw, n, n))
+    G1, G2, G3 = (rng.standard_normal((n, n)) for _ in range(3))
+    ref = O.g_iw_to_tau(G, G1, G2, G3, beta, ntau, method="direct")
+    got = O.g_iw_to_tau(G, G1, G2, G3, beta, ntau, tau=tau_grid(beta, ntau))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def _int_tau_power(k, w, beta):
+    """int_0^beta tau^k exp(i w tau) dtau for fermionic w (exp(i w beta) = -1),
+    by parts: I_k = -beta^k/(i w) - k/(i w) I_{k-1}, I_0 = -2/(i w)."""
+    iw = 1j * w
+    I = -2.0 / iw
+    for p in range(1, k + 1):
+        I = -beta ** p / iw - p / iw * I
+    return I
+
+
+def test_cubic_is_integrated_exactly_on_a_power_grid():
+    beta = 7.0
+    tau = power_tau_grid(beta, 4, 3)
+    a = [0.3, -1.1, 0.45, -0.07]
+    Y = sum(a[k] * tau ** k for k in range(4))[:, None, None]
+    niw = 400
+    got, _ = O.sigma_tau_to_iw(Y, beta, niw, tau=tau)
+    w = matsubara(beta, niw)
+    want = sum(a[k] * np.array([_int_tau_power(k, x, beta) for x in w]) for k in range(4))
+    np.testing.assert_allclose(got[:, 0, 0], want, rtol=0, atol=1e-11)
+
+
+def test_hf_green_function_on_a_power_grid():
+    s = generic_system(6, 3, beta=30.0)
+    F = s.h
+    eps, _ = R.generalized_eig(F, s.S)
+    mu = R.mu_closed_form(eps, s.nelec, s.beta)
+    tau = power_tau_grid(s.beta, 5, 6)
+    niw = 8192
+    G = R.hf_green_iw(s.S, F, mu, s.beta, niw)
+    got = O.g_iw_to_tau(G, *O.tail_moments(s.S, F, mu), s.beta, len(tau), tau=tau)
+    want = R.hf_green_tau(s.S, F, mu, s.beta, tau)
+    assert np.max(np.abs(got - want)) < 1e-9
