@@ -170,10 +170,28 @@ int gf2_sigma_tau(gf2_ctx *ctx, const gf2_dims *dims, int prec,
  *       G ~ G1/(iw) + G2/(iw)^2 + G3/(iw)^3;
  *       out = G(tau) device [ntau][n][n] FP64: the tail-subtracted
  *       Matsubara sum plus the tail in closed form.  moment1_out unused.
+ * The tau grid is uniform, tau_k = k beta/(ntau-1), unless a grid was set
+ * with gf2_set_tau_grid; then dims->ntau must equal its length and its last
+ * point must equal dims->beta (GF2_EINVAL otherwise).
  * Works on any n (no system needed).
  */
 int gf2_fourier(gf2_ctx *ctx, const gf2_dims *dims, int dir, const void *in,
                 const double *moments, void *out, double *moment1_out);
+
+/* gf2_set_tau_grid: a non-equidistant imaginary-time grid for this context
+ * (Implementation section: the paper uses a non-equidistant grid of a few
+ * thousand points).  tau: device [ntau] FP64, copied; tau_0 = 0 < tau_1 <
+ * ... < tau_{ntau-1} = beta, symmetric about beta/2 (tau_{M-k} = beta -
+ * tau_k, so G(-tau_k) = -G(tau_{M-k}) stays on the grid).  Every later
+ * gf2_fourier, gf2_iterate and gf2_iterate_batched call on the context
+ * samples G(tau), Sigma(tau) at these points: the spline integral and the
+ * Matsubara sum use the actual spacings (FP64 MFMA GEMMs against weight
+ * tables built on first use for each (niw, beta)).  ntau = 0 (tau may be
+ * NULL) restores the uniform grid.  Synchronises the context's stream.
+ * Errors: GF2_EINVAL for ntau < 4, a NULL grid, or a grid that does not
+ * start at 0, increase strictly, or mirror about its midpoint.
+ */
+int gf2_set_tau_grid(gf2_ctx *ctx, int ntau, const double *tau);
 
 /* gf2_dyson: Eq. (GF) at every Matsubara frequency for chemical potential
  * mu, with the system's S and the given F (device [n][n]) and

@@ -40,7 +40,7 @@ GF2_MU_SECANT = 2
 
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
-            "gf2_iterate", "gf2_iterate_batched", "gf2_natural_occupations",
+            "gf2_iterate", "gf2_iterate_batched", "gf2_natural_occupations", "gf2_set_tau_grid",
             "gf2_profile_enable", "gf2_profile_read")
 
 GF2_KC_SIGMA_GEMM = 0
@@ -114,6 +114,7 @@ def load(path: str = None):
         "gf2_dyson": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
         "gf2_fock": ([vp, vp, vp], i),
         "gf2_natural_occupations": ([vp, vp, vp], i),
+        "gf2_set_tau_grid": ([vp, i, vp], i),
         "gf2_density_fock": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), vp, vp, vp, dp, vp,
                               vp, vp, dp], i),
         "gf2_iterate": ([vp, C.POINTER(gf2_dims), C.POINTER(gf2_params), C.POINTER(gf2_state),
@@ -209,6 +210,11 @@ def gf2_fock(ctx, P, F):
 
 def gf2_natural_occupations(ctx, P, occ):
     _check(load().gf2_natural_occupations(ctx, _ptr(P), _ptr(occ)))
+
+
+def gf2_set_tau_grid(ctx, tau):
+    """tau: device FP64 tensor of grid points, or None for the uniform grid."""
+    _check(load().gf2_set_tau_grid(ctx, 0 if tau is None else int(tau.numel()), _ptr(tau)))
 
 
 def gf2_density_fock(ctx, dims: gf2_dims, params: gf2_params, F_in, Sigma_iw, Sigma1, mu,

@@ -326,7 +326,8 @@ int gf2_ctx_destroy(gf2_ctx *c) {
                            &c->W2_64,    &c->W2_32,     &c->W2_b3,   &c->sig_T1,   &c->sig_X,    &c->sig_Gp,  &c->sig_Gq,
                            &c->sig_G,    &c->sig_Gb,    &c->sig_part, &c->four_c,  &c->four_C,
                            &c->four_fold, &c->four_twid, &c->dys_part, &c->dys_X,   &c->dys_aux,
-                           &c->dys_out,  &c->fock_part, &c->occ_ws, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
+                           &c->dys_out,  &c->fock_part, &c->occ_ws, &c->grid_tau, &c->grid_thom, &c->grid_W, &c->grid_T,
+                           &c->grid_coef, &c->grid_plan, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
                            &c->it_mom,   &c->it_Sig_new, &c->it_Pout, &c->it_Pin,  &c->it_F,
                            &c->it_tmp,   &c->it_hist,   &c->host_stage, &c->bat_tab,  &c->bat_boff,
                            &c->bat_out,  &c->sig_tab,  &c->it_red,  &c->bat_red};

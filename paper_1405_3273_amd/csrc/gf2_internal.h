@@ -82,6 +82,14 @@ struct gf2_ctx {
     gf2::DevBuf dys_part, dys_X, dys_aux, dys_out;
     gf2::DevBuf fock_part;
     gf2::DevBuf occ_ws;                   // natural occupations: L, L^T, P L, A, status
+    // non-equidistant tau grid (gf2_set_tau_grid); grid_ntau == 0: uniform grid
+    int grid_ntau = 0;
+    std::vector<double> grid_host;
+    gf2::DevBuf grid_tau, grid_thom;      // tau_k; Thomas factors of the spline system
+    gf2::DevBuf grid_W, grid_T;           // tau->iw weights, iw->tau cos/sin table
+    int grid_w_niw = 0, grid_t_niw = 0;   // niw the tables were built for
+    double grid_w_beta = 0.0, grid_t_beta = 0.0;
+    gf2::DevBuf grid_coef, grid_plan;     // spline coefficients; planar [2 niw][n n] work
     gf2::DevBuf it_Sig_iw, it_G_iw, it_Sig1, it_mom, it_Sig_new, it_Pout, it_Pin, it_F, it_tmp;
     gf2::DevBuf it_hist;                  // Pulay history on the device: [2*depth][n][n]
     gf2::DevBuf it_red;                   // inner-loop reduction results

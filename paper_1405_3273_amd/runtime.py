@@ -83,6 +83,17 @@ class Gf2:
         L.gf2_fock(self.ctx, P, F)
         return F
 
+    def set_tau_grid(self, tau):
+        """Sample G(tau), Sigma(tau) on the grid tau (ntau points; None: uniform)."""
+        if tau is None:
+            L.gf2_set_tau_grid(self.ctx, None)
+            self._grid = None
+            return
+        t = self.torch.as_tensor(tau, dtype=self.torch.float64).to(self.device).contiguous()
+        L.gf2_set_tau_grid(self.ctx, t)
+        self._grid = t
+        self.dims = self.dims_with(ntau=int(t.numel()))
+
     def natural_occupations(self, P):
         """Natural occupation numbers of the density P, largest first."""
         occ = self._empty(self.n)
