@@ -684,25 +684,39 @@ template <int MODE, int KT> struct S23Threads {
     static constexpr int value = (MODE == MODE_F64 && KT <= 7) ? 1024 : 512;
 };
 
+// p tiles per workgroup: the FP32 form up to KT = 7 takes two adjacent p tiles
+// per wave (each T1 operand load and each G(tau) read from LDS then feeds two
+// MFMAs; 206 registers at KT = 7).  Above KT = 7 the doubled G(-tau) columns
+// would leave one workgroup per CU, and the FP64 form has 128 registers.
+template <int MODE, int KT> struct S23Pt {
+    static constexpr int value = (MODE == MODE_F32 && KT <= 7) ? 2 : 1;
+};
+static int s23_pt(int mode, int kt) { return (mode == MODE_F32 && kt <= 7) ? 2 : 1; }
+// workgroups per (tau, n): one per group of S23Pt p tiles
+static int s23_groups(int mode, int kt) { return (kt + s23_pt(mode, kt) - 1) / s23_pt(mode, kt); }
+
 template <int MODE, int KT, bool GLDS>
 __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23Args> ref) {
     using T = typename ModeT<MODE>::in_t;
     using acc_t = typename ModeT<MODE>::acc_t;
     constexpr int P16 = 16 * KT;
     constexpr int SL = P16 + S23Geom<MODE>::pad;
+    constexpr int PT = S23Pt<MODE, KT>::value;
+    constexpr int KTP = (KT + PT - 1) / PT;
     extern __shared__ __attribute__((aligned(16))) unsigned char s23_smem[];
 
     S23Args a;
     int L;
-    if (!kresolve(ref, ref.one.nb * ref.one.n * KT, a, L)) return;
+    if (!kresolve(ref, ref.one.nb * ref.one.n * KTP, a, L)) return;
     const int N = a.n;
-    const int pt = L % KT;
-    const int nn = (L / KT) % N;
-    const int t = L / (KT * N);
+    const int pt = (L % KTP) * PT;                 // first p tile of the workgroup
+    const int nn = (L / KTP) % N;
+    const int t = L / (KTP * N);
     const int S = (N + 3) >> 2;                    // q steps of 4
+    const bool two = PT == 2 && pt + 1 < KT;       // wave-uniform
 
     T *Gl = reinterpret_cast<T *>(s23_smem);
-    T *Bl = Gl + (GLDS ? P16 * SL : 0);            // [4S][16]: G(-tau)[q][16 pt + c]
+    T *Bl = Gl + (GLDS ? P16 * SL : 0);            // [4S][16 PT]: G(-tau)[q][16 pt + c]
     const T *Gsrc = static_cast<const T *>(a.Gp) + (size_t)t * P16 * SL;
     const T *Gb = static_cast<const T *>(a.Gb) + (size_t)t * N * N;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -717,13 +731,13 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     // step GW u + j <-> q = 4 GW u + GW a + j (a = lane/16), so that a lane
     // reads GW consecutive q of one slab row with one 16-B load; the
     // remaining q (and every q when N % GW != 0) as step s <-> q = 4s + a.
-    // Bl[step][a][c] = G(-tau)[q(step, a)][16 pt + c].
+    // Bl[step][a][c] = G(-tau)[q(step, a)][16 pt + c], c < 16 PT.
     constexpr int GW = 16 / (int)sizeof(T);      // q per 16-B load: 4 (FP32), 2 (FP64)
     // (FP64 keeps one q per load: its grouped form needs too many registers)
     const bool vq = (MODE != MODE_F64) && (N % GW == 0);
     const int U = vq ? N / (4 * GW) : 0;
-    for (int e = tid; e < 4 * S * 16; e += nth) {
-        const int st = e >> 6, ga = (e >> 4) & 3, p = 16 * pt + (e & 15);
+    for (int e = tid; e < 4 * S * 16 * PT; e += nth) {
+        const int st = e / (64 * PT), ga = (e / (16 * PT)) & 3, p = 16 * pt + e % (16 * PT);
         const int q = (st < GW * U) ? 4 * GW * (st / GW) + GW * ga + (st % GW) : 4 * st + ga;
         Bl[e] = (q < N && p < N) ? Gb[(size_t)q * N + p] : T(0);
     }
@@ -783,29 +797,38 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     }
     for (; i < N; i += nw) {
         const T *slab = slab_of(i);
-        acc_t acc1[KT];
+        acc_t acc1[KT], acc1b[PT == 2 ? KT : 1];   // p tiles pt, pt + 1
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) acc1[kt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kt = 0; kt < (PT == 2 ? KT : 1); ++kt) acc1b[kt] = acc_t{0, 0, 0, 0};
 
         // ---- Y^T[k][p] = sum_q T1[q][k] Gb[q][p]
-        auto mma = [&](T av, T bv, int kt) {
+        auto mma = [&](acc_t &ac, T av, T bv) {
             if constexpr (MODE == MODE_F64)
-                acc1[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1[kt], 0, 0, 0);
+                ac = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, ac, 0, 0, 0);
             else
-                acc1[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc1[kt], 0, 0, 0);
+                ac = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, ac, 0, 0, 0);
+        };
+        const int bl_off = 16 * PT * g + c;
+        auto step = [&](auto av_of, int st) {
+            const T bv = Bl[st * 64 * PT + bl_off];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) mma(acc1[kt], av_of(kt), bv);
+            if constexpr (PT == 2) {
+                if (two) {
+                    const T bw = Bl[st * 64 * PT + bl_off + 16];
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt) mma(acc1b[kt], av_of(kt), bw);
+                }
+            }
         };
         auto stepg = [&](const qv_t(&r)[KT], int u) {
 #pragma unroll
-            for (int j = 0; j < GW; ++j) {
-                const T bv = Bl[(GW * u + j) * 64 + lane];
-#pragma unroll
-                for (int kt = 0; kt < KT; ++kt) mma(r[kt][j], bv, kt);
-            }
+            for (int j = 0; j < GW; ++j) step([&](int kt) { return r[kt][j]; }, GW * u + j);
         };
         auto step1 = [&](const T(&r)[KT], int st) {
-            const T bv = Bl[st * 64 + lane];
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt) mma(r[kt], bv, kt);
+            step([&](int kt) { return r[kt]; }, st);
         };
         if (U > 0) {
             // the first ungrouped step is loaded now; it is used last
@@ -840,58 +863,75 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
 
         // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p], one 16-row l tile at a time
         T *xbase = X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+        auto store = [&](T *xb, const acc_t &v, int lt) {
+            if constexpr (MODE == MODE_F64) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int l = 16 * lt + g + 4 * e;
+                    if (l < N) xb[l] = v[e];
+                }
+            } else {
+                const int l0 = 16 * lt + 4 * g;
+                if (vec4 && l0 < N) {
+                    *reinterpret_cast<float4 *>(xb + l0) = make_float4(v[0], v[1], v[2], v[3]);
+                } else if (!vec4) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (l0 + e < N) xb[l0 + e] = v[e];
+                }
+            }
+        };
+        // the e-th MFMA of k tile kt contracts k = 16 kt + 4e + a; the last tile
+        // goes first and runs only its MFMAs with e < elast
+        auto gop = [&](const T *grow, int kt, T (&gv)[4]) {
+            if constexpr (MODE == MODE_F64) {
+                const double2 g0 = *reinterpret_cast<const double2 *>(grow + 16 * kt);
+                const double2 g1 = *reinterpret_cast<const double2 *>(grow + 16 * kt + 2);
+                gv[0] = g0.x; gv[1] = g0.y; gv[2] = g1.x; gv[3] = g1.y;
+            } else {
+                const float4 g4 = *reinterpret_cast<const float4 *>(grow + 16 * kt);
+                gv[0] = g4.x; gv[1] = g4.y; gv[2] = g4.z; gv[3] = g4.w;
+            }
+        };
 #pragma unroll 1
         for (int lt = 0; lt < KT; ++lt) {
-            // two accumulation chains (even / odd k tiles), added at the end
-            acc_t acc2 = acc_t{0, 0, 0, 0}, acc2b = acc_t{0, 0, 0, 0};
             const T *grow = Gop + (16 * lt + c) * SL + 4 * g;
-            // e-th MFMA of tile kt: k = 16 kt + 4e + a.  The last tile goes
-            // first and runs only its MFMAs with e < elast.
-            auto ktile = [&](acc_t &ac, int kt, bool last) {
-                if constexpr (MODE == MODE_F64) {
-                    const double2 g0 = *reinterpret_cast<const double2 *>(grow + 16 * kt);
-                    const double2 g1 = *reinterpret_cast<const double2 *>(grow + 16 * kt + 2);
-                    ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.x, acc1[kt][0], ac, 0, 0, 0);
-                    if (!last || elast > 1)
-                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g0.y, acc1[kt][1], ac, 0, 0, 0);
-                    if (!last || elast > 2)
-                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.x, acc1[kt][2], ac, 0, 0, 0);
-                    if (!last || elast > 3)
-                        ac = __builtin_amdgcn_mfma_f64_16x16x4f64(g1.y, acc1[kt][3], ac, 0, 0, 0);
-                } else {
-                    const float4 gv = *reinterpret_cast<const float4 *>(grow + 16 * kt);
-                    ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, acc1[kt][0], ac, 0, 0, 0);
-                    if (!last || elast > 1)
-                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, acc1[kt][1], ac, 0, 0, 0);
-                    if (!last || elast > 2)
-                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, acc1[kt][2], ac, 0, 0, 0);
-                    if (!last || elast > 3)
-                        ac = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, acc1[kt][3], ac, 0, 0, 0);
-                }
-            };
-            ktile(((KT - 1) & 1) ? acc2b : acc2, KT - 1, true);
-#pragma unroll
-            for (int kt = 0; kt < KT - 1; ++kt) ktile((kt & 1) ? acc2b : acc2, kt, false);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc2[e] += acc2b[e];
-            if (p < N) {
-                if constexpr (MODE == MODE_F64) {
+            if constexpr (PT == 2) {
+                // one chain per p tile, the G(tau) operand shared
+                acc_t acc2 = acc_t{0, 0, 0, 0}, acc3 = acc_t{0, 0, 0, 0};
+                auto ktile = [&](int kt, bool last) {
+                    T gv[4];
+                    gop(grow, kt, gv);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int l = 16 * lt + g + 4 * e;
-                        if (l < N) xbase[l] = acc2[e];
+                        if (e > 0 && last && elast <= e) break;
+                        mma(acc2, gv[e], acc1[kt][e]);
+                        if (two) mma(acc3, gv[e], acc1b[kt][e]);
                     }
-                } else {
-                    const int l0 = 16 * lt + 4 * g;
-                    if (vec4 && l0 < N) {
-                        *reinterpret_cast<float4 *>(xbase + l0) =
-                            make_float4(acc2[0], acc2[1], acc2[2], acc2[3]);
-                    } else if (!vec4) {
+                };
+                ktile(KT - 1, true);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (l0 + e < N) xbase[l0 + e] = acc2[e];
+                for (int kt = 0; kt < KT - 1; ++kt) ktile(kt, false);
+                if (p < N) store(xbase, acc2, lt);
+                if (two && p + 16 < N) store(xbase + (size_t)16 * R * N, acc3, lt);
+            } else {
+                // two accumulation chains (even / odd k tiles), added at the end
+                acc_t acc2 = acc_t{0, 0, 0, 0}, acc2b = acc_t{0, 0, 0, 0};
+                auto ktile = [&](acc_t &ac, int kt, bool last) {
+                    T gv[4];
+                    gop(grow, kt, gv);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (e > 0 && last && elast <= e) break;
+                        mma(ac, gv[e], acc1[kt][e]);
                     }
-                }
+                };
+                ktile(((KT - 1) & 1) ? acc2b : acc2, KT - 1, true);
+#pragma unroll
+                for (int kt = 0; kt < KT - 1; ++kt) ktile((kt & 1) ? acc2b : acc2, kt, false);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc2[e] += acc2b[e];
+                if (p < N) store(xbase, acc2, lt);
             }
         }
     }
@@ -1497,13 +1537,15 @@ static size_t s23_lds_b(int mode, int n) {
 
 template <int MODE, int KT>
 static bool s23_glds() {
-    return s23_lds_g<MODE, KT>() + s23_lds_b(MODE, 16 * KT) <= (size_t)120 * 1024;
+    return s23_lds_g<MODE, KT>() + S23Pt<MODE, KT>::value * s23_lds_b(MODE, 16 * KT) <=
+           (size_t)120 * 1024;
 }
 
 // default waves per S23 workgroup: ~16 resident waves per CU
 template <int MODE, int KT>
 static int s23_default_waves(int n) {
-    const size_t lds = (s23_glds<MODE, KT>() ? s23_lds_g<MODE, KT>() : 0) + s23_lds_b(MODE, n);
+    const size_t lds = (s23_glds<MODE, KT>() ? s23_lds_g<MODE, KT>() : 0) +
+                       S23Pt<MODE, KT>::value * s23_lds_b(MODE, n);
     const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
     return std::min(S23Threads<MODE, KT>::value / 64, std::max(4, 16 / per_cu));
 }
@@ -1511,12 +1553,14 @@ static int s23_default_waves(int n) {
 template <int MODE, int KT>
 static int launch_s23_kt(hipStream_t st, dim3 grid, int waves, size_t lds_b, const KRef<S23Args> &r,
                          bool attr_only) {
+    // lds_b: the G(-tau) columns of one p tile; S23Pt tiles per workgroup
+    constexpr int PT = S23Pt<MODE, KT>::value;
     const bool glds = s23_glds<MODE, KT>();
-    const size_t lds = (glds ? s23_lds_g<MODE, KT>() : 0) + lds_b;
+    const size_t lds = (glds ? s23_lds_g<MODE, KT>() : 0) + PT * lds_b;
     waves = std::min(waves, S23Threads<MODE, KT>::value / 64);
     const void *fn = glds ? (const void *)k_s23<MODE, KT, true> : (const void *)k_s23<MODE, KT, false>;
     // the same limit (the largest any n of this KT needs) on every path
-    const size_t lds_max = (glds ? s23_lds_g<MODE, KT>() : 0) + s23_lds_b(MODE, 16 * KT);
+    const size_t lds_max = (glds ? s23_lds_g<MODE, KT>() : 0) + PT * s23_lds_b(MODE, 16 * KT);
     GF2_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
     if (attr_only) return GF2_OK;
     if (glds) hipLaunchKernelGGL((k_s23<MODE, KT, true>), grid, dim3(64 * waves), lds, st, r);
@@ -1874,7 +1918,8 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
         if (prof) prof_end(c, ph, fl);
     }
     {
-        const dim3 grid(xcd_grid((long long)nb * p.n * p.KT));
+        const int groups = (p.mode == MODE_BF3) ? p.KT : s23_groups(p.mode, p.KT);
+        const dim3 grid(xcd_grid((long long)nb * p.n * groups));
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_S23) : -1;
         if (p.mode == MODE_BF3) {
             KRef<S23b3Args> r{};
@@ -2118,7 +2163,8 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                 std::vector<S23Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s23(plans[s], nb_of(s)));
-                    boff.push_back(boff.back() + nb_of(s) * plans[s].n * plans[s].KT);
+                    boff.push_back(boff.back() +
+                                   nb_of(s) * plans[s].n * s23_groups(prec, plans[s].KT));
                     lds = std::max(lds, s23_lds_b(prec, plans[s].n));
                 }
                 push_table(buf, tab, boff, gl);
