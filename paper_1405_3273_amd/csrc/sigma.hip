@@ -897,21 +897,30 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
         for (int lt = 0; lt < KT; ++lt) {
             const T *grow = Gop + (16 * lt + c) * SL + 4 * g;
             if constexpr (PT == 2) {
-                // one chain per p tile, the G(tau) operand shared
-                acc_t acc2 = acc_t{0, 0, 0, 0}, acc3 = acc_t{0, 0, 0, 0};
+                // per p tile two chains (even / odd k tiles, added at the end,
+                // as in the one-tile form); the G(tau) operand is shared
+                acc_t acc2 = acc_t{0, 0, 0, 0}, acc2b = acc_t{0, 0, 0, 0};
+                acc_t acc3 = acc_t{0, 0, 0, 0}, acc3b = acc_t{0, 0, 0, 0};
                 auto ktile = [&](int kt, bool last) {
                     T gv[4];
                     gop(grow, kt, gv);
+                    acc_t &a0 = (kt & 1) ? acc2b : acc2;
+                    acc_t &a1 = (kt & 1) ? acc3b : acc3;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (e > 0 && last && elast <= e) break;
-                        mma(acc2, gv[e], acc1[kt][e]);
-                        if (two) mma(acc3, gv[e], acc1b[kt][e]);
+                        mma(a0, gv[e], acc1[kt][e]);
+                        if (two) mma(a1, gv[e], acc1b[kt][e]);
                     }
                 };
                 ktile(KT - 1, true);
 #pragma unroll
                 for (int kt = 0; kt < KT - 1; ++kt) ktile(kt, false);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc2[e] += acc2b[e];
+                    acc3[e] += acc3b[e];
+                }
                 if (p < N) store(xbase, acc2, lt);
                 if (two && p + 16 < N) store(xbase + (size_t)16 * R * N, acc3, lt);
             } else {
