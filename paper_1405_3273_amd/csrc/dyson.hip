@@ -291,6 +291,8 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
 
         // physical (i, j) holds G[rinv(i)][perm(j)]
         const double iw2 = 1.0 / (w * w);
+        const bool en = full && a.mode == GF2_DYSON_ENERGY && Sig;
+        double e_r = 0.0, e_i = 0.0;   // this frequency: Re G.(mu S - F), Im G.S
 #pragma unroll
         for (int ia = 0; ia < RA; ++ia)
 #pragma unroll
@@ -299,16 +301,21 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 if (!(active && i < n && j < n)) continue;
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
-                acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
+                const size_t et = (size_t)gb * n + ga;
+                const double sv = a.S[et];
+                acc_tr += mr[ia][jb] * sv;
                 if (full) {
                     Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
-                    if (a.mode == GF2_DYSON_ENERGY && Sig) {
-                        const double2 sg = Sig[(size_t)gb * n + ga];
-                        acc_e += mr[ia][jb] * sg.x - mi[ia][jb] * sg.y;
+                    if (en) {
+                        e_r += mr[ia][jb] * fma(a.mu, sv, -a.F[et]);
+                        e_i += mi[ia][jb] * sv;
                     }
                 }
             }
+        // Re tr[G Sigma] from G A = 1: tr[G Sigma] = tr[G ((i w + mu) S - F)] - n
+        // (S and F are small and stay in L2; Sigma(i w) is not read a second time)
+        if (en) acc_e += e_r - w * e_i - (tid == 0 ? (double)n : 0.0);
     }
     __syncthreads();
 
@@ -497,6 +504,8 @@ __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, cons
         }
         // physical (i, j) holds G[rinv(i)][perm(j)]
         const double iw2 = 1.0 / (w * w);
+        const bool en = full && a.mode == GF2_DYSON_ENERGY && Sig;
+        double e_r = 0.0, e_i = 0.0;   // this frequency: Re G.(mu S - F), Im G.S
 #pragma unroll
         for (int ia = 0; ia < RA; ++ia)
 #pragma unroll
@@ -505,16 +514,20 @@ __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, cons
                 if (!(i < n && j < n)) continue;
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
-                acc_tr += mr[ia][jb] * a.S[(size_t)gb * n + ga];
+                const size_t et = (size_t)gb * n + ga;
+                const double sv = a.S[et];
+                acc_tr += mr[ia][jb] * sv;
                 if (full) {
                     Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
-                    if (a.mode == GF2_DYSON_ENERGY && Sig) {
-                        const double2 sg = Sig[(size_t)gb * n + ga];
-                        acc_e += mr[ia][jb] * sg.x - mi[ia][jb] * sg.y;
+                    if (en) {
+                        e_r += mr[ia][jb] * fma(a.mu, sv, -a.F[et]);
+                        e_i += mi[ia][jb] * sv;
                     }
                 }
             }
+        // Re tr[G Sigma] = Re tr[G ((i w + mu) S - F)] - n  (G A = 1)
+        if (en) acc_e += e_r - w * e_i - (lane == 0 ? (double)n : 0.0);
     }
     // wave reductions (fixed order)
     double v0 = acc_tr, v1 = acc_e;
