@@ -27,7 +27,11 @@ Readings for what the paper leaves open (tolerances and order):
   P_in <- sum_i c_i (P_in,i + (1 - a_P) r_i).  With ``mix_depth = 1`` this
   is exactly the paper's damping P_in <- (1 - a_P) P_out + a_P P_in.  The
   mixing history starts empty in every outer iteration.  If the small
-  bordered system is singular the history is cut to the newest pair.
+  bordered system is singular the history is cut to the newest pair; a
+  pass whose max|r| exceeds ``PULAY_RESTART`` (10) times the smallest
+  max|r| of the inner loop so far empties the history before its pair is
+  added (a damped step; extrapolation over a diverging history is what
+  makes Pulay mixing unstable).
   The very first pass of the run (core guess F = h) has no P_in: its
   P_out simply becomes the next P_in;
 * on convergence the inner loop returns mu, P = P_out and F = F(P_out);
@@ -90,6 +94,11 @@ class OuterReport:
     n_inner: int
     n_eval: int
     extras: dict = field(default_factory=dict)
+
+
+# A pass whose max|P_out - P_in| exceeds this factor times the smallest one of
+# the inner loop so far drops the Pulay history (restart with a damped step).
+PULAY_RESTART = 10.0
 
 
 def pulay_mix(hist, damp):
@@ -157,6 +166,7 @@ def inner_loop(sysm, params: Params, F, P_in, mu0, Sigma_iw, Sigma1):
     n_eval = 0
     hist = []
     slope = None
+    rbest = float("inf")
     for it in range(1, params.max_inner + 1):
         mu, ne, slope = find_mu(sysm.nelec, S, F, Sigma_iw, Sigma1, beta, niw, mu,
                                 halfwidth=params.mu_halfwidth, tol_mu=params.tol_mu,
@@ -170,8 +180,12 @@ def inner_loop(sysm, params: Params, F, P_in, mu0, Sigma_iw, Sigma1):
             P_next = P_out
         else:
             r = P_out - P_in
-            if float(np.max(np.abs(r))) < params.tol_P:
+            rn = float(np.max(np.abs(r)))
+            if rn < params.tol_P:
                 return mu, P_out, fock(h, v, P_out), G, mom, it, n_eval
+            if rn > PULAY_RESTART * rbest:
+                hist = []           # restart: the mix below is a damped step
+            rbest = min(rbest, rn)
             hist.append((P_in, r))
             hist = hist[-max(1, params.mix_depth):]
             P_next, hist = pulay_mix(hist, params.damp_P)

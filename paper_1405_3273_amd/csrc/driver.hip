@@ -348,6 +348,9 @@ __global__ void k_pulay_mix(int ne, const double *__restrict__ slots, SlotList L
 
 static unsigned grid_for(size_t ne) { return (unsigned)std::min<size_t>((ne + 255) / 256, 1024); }
 
+// Pulay restart factor (see InnerLoop::on_red)
+constexpr double PULAY_RESTART = 10.0;
+
 struct Pulay {
     int depth = 1;
     // device slots: x_a, r_a (ring of depth entries), host B_ab = <r_a, r_b>
@@ -407,6 +410,7 @@ struct InnerLoop {
     bool have_Pin = false;
     double mu = 0.0, slope = 0.0, trPS = 0.0, e2b = 0.0;
     double rprev = INFINITY;   // max|P_out - P_in| of the previous pass
+    double rbest = INFINITY;   // smallest max|P_out - P_in| of this inner loop
     double tol_pass = 0.0;     // mu acceptance of the current pass
     int it = 0, n_inner = 0, n_eval = 0, phase = 0, want = 0;
 
@@ -453,6 +457,7 @@ struct InnerLoop {
         phase = 0;
         want = 0;
         rprev = INFINITY;
+        rbest = INFINITY;
         tol_pass = pass_tolerance();
         ms.start(p, mu, slope, tol_pass);
         return GF2_OK;
@@ -502,6 +507,10 @@ struct InnerLoop {
                 return GF2_OK;
             }
             rprev = h[0];
+            // restart: a residual more than PULAY_RESTART times the best one of
+            // this inner loop drops the history (the mix is a damped step)
+            if (h[0] > PULAY_RESTART * rbest) pl.order.clear();
+            rbest = std::fmin(rbest, h[0]);
             // push (P_in, r = P_out - P_in), dropping the oldest beyond depth
             if ((int)pl.order.size() == pl.depth) pl.order.erase(pl.order.begin());
             const int s = pl.free_slot();
