@@ -130,3 +130,22 @@ def test_hartree_fock_inner_loop_reaches_closed_form_fixed_point():
     assert np.max(np.abs(P - P_ref)) < 1e-8
     assert np.max(np.abs(F - O.fock(s.h, s.v, P))) < 1e-14
     assert np.trace(P @ s.S) == pytest.approx(s.nelec, abs=1e-9)
+
+
+def test_pulay_restart_factor_zero_is_plain_damping(monkeypatch):
+    """With the restart factor at 0 every pass empties the history, so the
+    inner loop takes exactly the steps of plain damping (mix_depth 1); Pulay
+    mixing reaches the same fixed point in fewer passes.  (A weakly coupled
+    system, v_iiii ~ 0.1 Eh, on which plain damping converges.)"""
+    import oracle.loop as LP
+    s = generic_system(6, 41, beta=30.0, niw=512, ntau=33, vdiag=0.1)
+    zero = np.zeros((s.n, s.n))
+    kw = dict(tol_P=1e-10, max_inner=300)
+    damped = O.inner_loop(s, O.Params(mix_depth=1, **kw), s.h.copy(), None, 0.0, None, zero)
+    mixed = O.inner_loop(s, O.Params(**kw), s.h.copy(), None, 0.0, None, zero)
+    monkeypatch.setattr(LP, "PULAY_RESTART", 0.0)
+    restarted = O.inner_loop(s, O.Params(**kw), s.h.copy(), None, 0.0, None, zero)
+    assert restarted[5] == damped[5] and restarted[6] == damped[6]     # passes, evaluations
+    np.testing.assert_array_equal(restarted[1], damped[1])
+    assert mixed[5] < damped[5]
+    assert np.max(np.abs(mixed[1] - damped[1])) < 1e-9
