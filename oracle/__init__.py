@@ -28,7 +28,7 @@ invariants or brute force) unless its docstring says "parity unpinned".
 """
 from .grids import tau_grid, matsubara
 from .sigma import (gbar_from_gtau, sigma_bruteforce, sigma_literal, sigma_factored,
-                    sigma_tau, bracket_W)
+                    sigma_tau, bracket_W, sigma_df, sigma_tau_df)
 from .fourier import sigma_tau_to_iw, g_iw_to_tau, spline_coefficients, moments_unit, tail_tau
 from .dyson import (tail_moments, green_iw, density_from_giw, particle_number, find_mu,
                     BracketError, NoConvergence)
@@ -40,7 +40,7 @@ from .occupations import natural_occupations
 __all__ = [
     "tau_grid", "matsubara",
     "gbar_from_gtau", "sigma_bruteforce", "sigma_literal", "sigma_factored", "sigma_tau",
-    "bracket_W",
+    "bracket_W", "sigma_df", "sigma_tau_df",
     "sigma_tau_to_iw", "g_iw_to_tau", "spline_coefficients", "moments_unit", "tail_tau",
     "tail_moments", "green_iw", "density_from_giw", "particle_number", "find_mu",
     "BracketError", "NoConvergence",

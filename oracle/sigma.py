@@ -96,3 +96,37 @@ def sigma_tau(G_tau: np.ndarray, v: np.ndarray, taus=None) -> np.ndarray:
     Gb = gbar_from_gtau(G_tau)
     ks = range(ntau) if taus is None else taus
     return np.stack([sigma_factored(G_tau[k], Gb[k], v, W) for k in ks])
+
+
+def sigma_df(G: np.ndarray, Gb: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Eq. (Sigma) with density-fitted integrals v_ijkl = sum_P B^P_ij B^P_kl
+    (the cheaper route the Implementation section proposes, recalled in the
+    Conclusions; its O(n^3 m) estimate holds for the direct term, the exchange
+    term below costs O(n^3 m^2)).
+
+    Substituting the factors into both integrals of Eq. (Sigma) and grouping
+    the sums gives, with X^{PQ} = B^P G B^Q (N x N, P, Q over the auxiliary
+    index) and Gb = G(-tau),
+
+        direct:   2 sum_{PQ} X^{PQ}_ij tr(X^{PQ} Gb)
+        exchange:   sum_{PQ} (X^{PQ} Gb X^{PQ})_ij
+        Sigma_ij = -(direct - exchange).
+
+    Written with matrix products as steps, P and Q looped in order.
+    """
+    m, n = B.shape[0], B.shape[1]
+    out = np.zeros((n, n))
+    for P in range(m):
+        Y = B[P] @ G
+        for Q in range(m):
+            X = Y @ B[Q]
+            t = float(np.sum(X * Gb.T))          # tr(X Gb)
+            out += 2.0 * t * X - X @ Gb @ X
+    return -out
+
+
+def sigma_tau_df(G_tau: np.ndarray, B: np.ndarray, taus=None) -> np.ndarray:
+    """sigma_df at every grid point (or the listed indices ``taus``)."""
+    Gb = gbar_from_gtau(G_tau)
+    ks = range(G_tau.shape[0]) if taus is None else taus
+    return np.stack([sigma_df(G_tau[k], Gb[k], B) for k in ks])
