@@ -107,3 +107,23 @@ def test_natural_occupations_errors(torch):
         L.gf2_natural_occupations(ctx, P, occ)
     assert e.value.code == L.GF2_ESTATE
     L.gf2_ctx_destroy(ctx)
+
+
+def test_natural_occupations_reject_an_indefinite_overlap(torch):
+    """An overlap that is invertible but not positive definite has no Cholesky
+    factor: GF2_EINVAL, and the library stays usable."""
+    from paper_1405_3273_amd import _lib as L
+    S = np.diag([1.0, 1.0, -0.5, 1.0])
+    g = _ctx_for_overlap(torch, S)
+    P = torch.eye(4, dtype=torch.float64, device="cuda")
+    occ = torch.empty(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.Gf2Error) as e:
+        L.gf2_natural_occupations(g.ctx, P, occ)
+    assert e.value.code == L.GF2_EINVAL
+    g.close()
+    rng = np.random.default_rng(9)
+    S2 = _overlap(rng, 5)
+    g2 = _ctx_for_overlap(torch, S2)
+    occ2 = g2.natural_occupations(torch.as_tensor(_density_with_occupations(rng, S2, np.full(5, 1.5))).cuda())
+    np.testing.assert_allclose(occ2.cpu().numpy(), 1.5, atol=1e-12)
+    g2.close()
