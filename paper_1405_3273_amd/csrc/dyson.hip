@@ -37,7 +37,8 @@ constexpr int DY_MAXTHREADS = 512;
 // both cases.
 struct DysonJob {
     int n, niw, mode;       // mode < 0: idle (batched rounds)
-    int p_in_lds;           // FULL/ENERGY: accumulate P in LDS (else in partP directly)
+    int p_in_lds;           // FULL/ENERGY: P accumulated in LDS: 1 whole, 2 upper triangle
+                            // (block class; P is symmetric), 0 in partP directly
     int nbl;                // workgroups of this job in the Dyson launch
     double beta, mu;
     const double *S, *Sinv, *F, *Sig1;   // Sig1 may be NULL
@@ -133,12 +134,15 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
     __shared__ int perm[DY_MAXN], rinv[DY_MAXN];
     __shared__ double red[2][DY_MAXTHREADS / 64];
     __shared__ int sing;
-    extern __shared__ double shP[];   // n*n when FULL/ENERGY and p_in_lds
+    extern __shared__ double shP[];   // FULL/ENERGY: n*n (p_in_lds 1) or n(n+1)/2 (2)
 
     const bool full = a.mode != GF2_DYSON_TRACE;
-    double *Pacc = a.p_in_lds ? shP : (a.partP + (size_t)lb * n * n);
-    if (full)
-        for (int e = tid; e < n * n; e += nthr) Pacc[e] = 0.0;
+    const int pm = a.p_in_lds;
+    double *Pacc = pm == 1 ? shP : (a.partP + (size_t)lb * n * n);
+    if (full) {
+        const int cnt = pm == 2 ? n * (n + 1) / 2 : n * n;
+        for (int e = tid; e < cnt; e += nthr) (pm == 2 ? shP : Pacc)[e] = 0.0;
+    }
     if (tid == 0) sing = 0;
 
     double acc_tr = 0.0, acc_e = 0.0;
@@ -305,7 +309,13 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 const double sv = a.S[et];
                 acc_tr += mr[ia][jb] * sv;
                 if (full) {
-                    Pacc[e] += mr[ia][jb] + a.mom[n * n + e] * iw2;
+                    const double pv = mr[ia][jb] + a.mom[n * n + e] * iw2;
+                    if (pm == 2) {
+                        // upper triangle, row-major: (ga, gb), ga <= gb
+                        if (ga <= gb) shP[ga * n - ga * (ga - 1) / 2 + (gb - ga)] += pv;
+                    } else {
+                        Pacc[e] += pv;
+                    }
                     if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
                     if (en) {
                         e_r += mr[ia][jb] * fma(a.mu, sv, -a.F[et]);
@@ -346,8 +356,14 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
             ps[3] = 0.0;
         }
     }
-    if (full && a.p_in_lds)
+    if (full && pm == 1)
         for (int e = tid; e < n * n; e += nthr) a.partP[(size_t)lb * n * n + e] = shP[e];
+    if (full && pm == 2)
+        for (int e = tid; e < n * n; e += nthr) {
+            const int r = e / n, q = e - r * n;
+            const int lo = min(r, q), hi = max(r, q);
+            a.partP[(size_t)lb * n * n + e] = shP[lo * n - lo * (lo - 1) / 2 + (hi - lo)];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -639,6 +655,9 @@ static void launch_moments(const DysonRef &g, int njobs, int maxne, hipStream_t 
 // P = (4/beta) sum_b partW[b] + G1 - (beta/2) G2.  Grid: x over 64-element
 // chunks, y over jobs; the four waves of a workgroup sum quarters of the
 // partials (four interleaved accumulators each) and are combined in order.
+// When the partials hold the upper triangle mirrored (p_in_lds 2), the tail
+// terms are taken from the upper triangle too, so P is exactly symmetric and
+// every term of an element comes from the same (a <= b) entries.
 __global__ __launch_bounds__(256) void k_reduce_P(DysonRef g) {
     const DysonJob a = job_of(g, blockIdx.y);
     if (a.mode <= GF2_DYSON_TRACE) return;
@@ -665,7 +684,12 @@ __global__ __launch_bounds__(256) void k_reduce_P(DysonRef g) {
     __syncthreads();
     if (wv == 0 && e < ne) {
         const double s = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
-        a.P[e] = (4.0 / a.beta) * s + a.mom[e] - 0.5 * a.beta * a.mom[ne + e];
+        int et = e;
+        if (a.p_in_lds == 2) {
+            const int r = e / a.n, c = e - r * a.n;
+            et = min(r, c) * a.n + max(r, c);
+        }
+        a.P[e] = (4.0 / a.beta) * s + a.mom[et] - 0.5 * a.beta * a.mom[ne + et];
     }
 }
 
@@ -777,12 +801,24 @@ static int dyson_slots(gf2_ctx *c, int n, int niw) {
 static int dyson_workgroups(int n, int slots) {
     return dyson_wave_class(dyson_class(n)) ? slots / DW : slots;
 }
-// P accumulation in LDS (FULL/ENERGY) while it keeps two workgroups per CU
-static size_t dyson_shm(int n, int mode) {
+// Where a FULL/ENERGY solve accumulates P (DysonJob::p_in_lds): the whole
+// matrix in LDS when it takes <= 32 KB (per wave slot in the wave class), else
+// in the block class its upper triangle (<= 104 KB: n <= 160; up to n = 112 it
+// keeps two workgroups of 4 waves per CU), else global memory.
+static int dyson_pmode(int n, int mode) {
     if (mode == GF2_DYSON_TRACE) return 0;
     const size_t ne8 = (size_t)n * n * 8;
-    const size_t need = dyson_wave_class(dyson_class(n)) ? DW * ne8 : ne8;
-    return need <= 32 * 1024 ? need : 0;
+    if (dyson_wave_class(dyson_class(n))) return DW * ne8 <= 32 * 1024 ? 1 : 0;
+    if (ne8 <= 32 * 1024) return 1;
+    return (size_t)n * (n + 1) / 2 * 8 <= 104 * 1024 ? 2 : 0;
+}
+static size_t dyson_shm(int n, int mode) {
+    const size_t ne8 = (size_t)n * n * 8;
+    switch (dyson_pmode(n, mode)) {
+    case 1: return dyson_wave_class(dyson_class(n)) ? DW * ne8 : ne8;
+    case 2: return (size_t)n * (n + 1) / 2 * 8;
+    default: return 0;
+    }
 }
 
 // P partials of a FULL/ENERGY solve: the wave class sums the DW slots of a
@@ -854,7 +890,6 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     const bool full = mode != GF2_DYSON_TRACE;
     const int nblocks = dyson_slots(c, n, niw);
     const size_t shm = dyson_shm(n, mode);
-    const bool p_in_lds = shm > 0;
 
     GF2_TRY(c->dys_X.ensure(6 * ne * 8));
     GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
@@ -865,7 +900,7 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     DysonRef g{};
     DysonJob &a = g.one;
     a.n = n; a.niw = niw; a.mode = mode;
-    a.p_in_lds = p_in_lds ? 1 : 0;
+    a.p_in_lds = dyson_pmode(n, mode);
     a.nbl = nblocks;
     a.beta = d->beta; a.mu = mu;
     a.S = c->S.as<double>(); a.Sinv = c->Sinv.as<double>(); a.F = F;
@@ -1041,7 +1076,7 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
         a.n = n;
         a.niw = q.d->niw;
         a.mode = q.mode;
-        a.p_in_lds = dyson_shm(n, q.mode) > 0 ? 1 : 0;
+        a.p_in_lds = dyson_pmode(n, q.mode);
         a.nbl = nbl[s];
         a.beta = q.d->beta;
         a.mu = q.mu;
