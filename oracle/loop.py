@@ -99,6 +99,9 @@ class OuterReport:
 # A pass whose max|P_out - P_in| exceeds this factor times the smallest one of
 # the inner loop so far drops the Pulay history (restart with a damped step).
 PULAY_RESTART = 10.0
+# Mixing coefficients larger than this in magnitude cut the history to the
+# newest pair, as a singular bordered system does.
+PULAY_CMAX = 20.0
 
 
 def pulay_mix(hist, damp):
@@ -121,6 +124,8 @@ def pulay_mix(hist, damp):
         rhs = np.zeros(k + 1)
         rhs[k] = 1.0
         c = _solve_pivoted(A, rhs)
+        if c is not None and k > 1 and float(np.max(np.abs(c[:k]))) > PULAY_CMAX:
+            c = None                # extrapolation too far: treated like a singular system
         if c is not None or k == 1:
             break
         hist = hist[-1:]

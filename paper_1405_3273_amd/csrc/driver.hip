@@ -348,8 +348,10 @@ __global__ void k_pulay_mix(int ne, const double *__restrict__ slots, SlotList L
 
 static unsigned grid_for(size_t ne) { return (unsigned)std::min<size_t>((ne + 255) / 256, 1024); }
 
-// Pulay restart factor (see InnerLoop::on_red)
+// Pulay restart factor (see InnerLoop::on_red) and the largest mixing
+// coefficient accepted before the history is cut to the newest pair
 constexpr double PULAY_RESTART = 10.0;
+constexpr double PULAY_CMAX = 20.0;
 
 struct Pulay {
     int depth = 1;
@@ -366,7 +368,8 @@ struct Pulay {
         return -1;
     }
     // coefficients c (sum c_a = 1) minimising |sum c_a r_a|; a singular
-    // system drops all but the newest pair
+    // system, or one whose coefficients exceed PULAY_CMAX, drops all but the
+    // newest pair
     std::vector<double> coef() {
         for (;;) {
             const int k = (int)order.size();
@@ -381,7 +384,12 @@ struct Pulay {
                 A[a * (k + 1) + k] = 1.0;
             }
             rhs[k] = 1.0;
-            if (solve_pivoted(k + 1, A, rhs, sol)) return std::vector<double>(sol.begin(), sol.begin() + k);
+            if (solve_pivoted(k + 1, A, rhs, sol)) {
+                double cmax = 0.0;
+                for (int a = 0; a < k; ++a) cmax = std::fmax(cmax, std::fabs(sol[a]));
+                // extrapolation too far: treated like a singular system
+                if (k == 1 || cmax <= PULAY_CMAX) return std::vector<double>(sol.begin(), sol.begin() + k);
+            }
             if (k == 1) return std::vector<double>(1, 1.0);
             order.erase(order.begin(), order.end() - 1);
         }
