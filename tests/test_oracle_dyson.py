@@ -149,3 +149,19 @@ def test_pulay_restart_factor_zero_is_plain_damping(monkeypatch):
     np.testing.assert_array_equal(restarted[1], damped[1])
     assert mixed[5] < damped[5]
     assert np.max(np.abs(mixed[1] - damped[1])) < 1e-9
+
+
+def test_pulay_caps_large_coefficients():
+    """Nearly parallel residuals make the minimising coefficients huge; above
+    the cap the history is cut to the newest pair (a damped step)."""
+    rng = np.random.default_rng(4)
+    x1, x2 = rng.standard_normal((2, 4, 4))
+    r = rng.standard_normal((4, 4))
+    hist = [(x1, r), (x2, 1.001 * r + 1e-9 * rng.standard_normal((4, 4)))]
+    got, h = pulay_mix(hist, 0.3)
+    assert len(h) == 1
+    assert np.allclose(got, x2 + 0.7 * hist[1][1], atol=1e-14)
+    # well-separated residuals keep both pairs
+    hist = [(x1, r), (x2, rng.standard_normal((4, 4)))]
+    _, h = pulay_mix(hist, 0.3)
+    assert len(h) == 2
