@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 METRIC = "GF2 iterations/s + Σ(τ) TFLOP/s at N=100,nτ=512; FP32/BF16-split vs FP64"
 
 PEAK = {  # MI355X published dense peaks
-    "fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "hbm": 8.0e12, "fp64_vector": 78.6e12,
+    "fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "bf16x6": 2.5e15, "hbm": 8.0e12, "fp64_vector": 78.6e12,
 }
 
 WORKLOADS = {
@@ -124,16 +124,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--workload", default="n100", choices=sorted(WORKLOADS))
-    ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3",
+    ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3,bf16x6",
                     help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mu-tol-rel", type=float, default=1e-2,
                     help="inexact mu search in early inner passes: tolerance\n"
                          "max(tol_N, rel * max|dP| of the previous pass); each inner loop still\n"
                          "ends on a pass that used tol_N (0 = tol_N throughout)")
-    ap.add_argument("--forms", default="fp64,bf16x3",
+    ap.add_argument("--forms", default="fp64,bf16x3,bf16x6",
                     help="other Sigma precisions run through the same iterations from the same\n"
                          "start, for the whole-iteration speedup and energy difference against\n"
                          "the FP64 form ('' to skip)")
@@ -210,9 +210,10 @@ def main():
                 "traffic": measured_traffic(dom, args.workload, args.prec),
                 "kernel": dom, "launches": cnt, "avg_launch_ms": avg_s * 1e3,
                 "work_per_launch": per_launch}
-    if bound == "mfma" and args.prec == "bf16x3":
-        roofline["note"] = ("BF16x3 issues 3 bf16 MFMA products per algorithmic FP32 MAC: "
-                            "frac is at most 1/3 against the bf16 peak")
+    if bound == "mfma" and args.prec in ("bf16x3", "bf16x6"):
+        k = 3 if args.prec == "bf16x3" else 6
+        roofline["note"] = (f"{args.prec} issues {k} bf16 MFMA products per algorithmic FP32 MAC: "
+                            f"frac is at most 1/{k} against the bf16 peak")
     classes = {k: {"ms": v[0], "launches": v[1],
                    "rate": (v[2] / (v[0] / 1e3) / (1e9 if kind[k][0] == "hbm" else 1e12))
                    if v[0] > 0 else None,
@@ -281,7 +282,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": desc, "sigma_arithmetic": args.prec,
                    "other_stages": "f64", "inner_tol_P": prm.tol_P, "damp_Sigma": prm.damp_Sigma,

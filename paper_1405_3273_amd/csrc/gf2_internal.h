@@ -40,7 +40,9 @@ struct DevBuf {
 };
 
 // Sigma(tau) arithmetic modes (match GF2_PREC_*).
-enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2 };
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2, MODE_BF6 = 3 };
+// BF16 planes per FP32 operand of a split-precision mode (0: not split).
+constexpr int split_planes(int mode) { return mode == MODE_BF3 ? 2 : mode == MODE_BF6 ? 3 : 0; }
 
 }  // namespace gf2
 

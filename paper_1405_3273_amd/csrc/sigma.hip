@@ -15,10 +15,14 @@
 // in FP64 in a fixed order, so results do not depend on scheduling.
 //
 // Arithmetic: FP64 MFMA (v_mfma_f64_16x16x4f64), FP32 MFMA
-// (v_mfma_f32_16x16x4f32), or BF16x3: each FP32 operand x is split into
-// hi = bf16(x), lo = bf16(x - hi) and a*b ~ hi_a*lo_b + lo_a*hi_b + hi_a*hi_b
-// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  In S4 the FP32
-// accumulators are flushed into FP64 registers every 512 K.
+// (v_mfma_f32_16x16x4f32), or split BF16 on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation: each FP32 operand x is split into bf16 terms
+// x = h + m (+ l), and of the products of the terms those of order 1 and
+// 2^-8 (BF16x3: h*h, h*m, m*h) or also 2^-16 (BF16x6: m*m, h*l, l*h) are
+// issued (the two- and three-term splits of Henry, Tang and Heinecke, "Leveraging
+// the bfloat16 artificial intelligence datatype for higher-precision
+// computations", ARITH 2019).  In S4 the FP32 accumulators are flushed into
+// FP64 registers every 512 K.
 #include "gf2_internal.h"
 
 #include <algorithm>
@@ -56,6 +60,7 @@ template <int MODE> struct ModeT;
 template <> struct ModeT<MODE_F64> { using in_t = double; using acc_t = v4d; static constexpr int BK = 16; };
 template <> struct ModeT<MODE_F32> { using in_t = float;  using acc_t = v4f; static constexpr int BK = 16; };
 template <> struct ModeT<MODE_BF3> { using in_t = float;  using acc_t = v4f; static constexpr int BK = 32; };
+template <> struct ModeT<MODE_BF6> { using in_t = float;  using acc_t = v4f; static constexpr int BK = 32; };
 
 struct GemmArgs {
     const void *A;
@@ -134,13 +139,18 @@ constexpr int NTHREADS = 256;
 constexpr int BM = 128;  // 4 waves x 2 row tiles x 16
 constexpr int RT = 2;    // row tiles per wave
 
-// x = hi + lo + O(2^-16 |x|): hi = bf16(x), lo = bf16(x - hi), round to nearest even
-// (v_cvt_pk_bf16_f32).
-__device__ __forceinline__ void split_bf16(float x, unsigned short &hi, unsigned short &lo) {
-    const __bf16 h = (__bf16)x;
-    const __bf16 l = (__bf16)(x - (float)h);
-    hi = __builtin_bit_cast(unsigned short, h);
-    lo = __builtin_bit_cast(unsigned short, l);
+// NP-term split, x = o[0] + ... + o[NP-1] + O(2^-8NP |x|): each term is the
+// bf16 rounding (nearest even, v_cvt_pk_bf16_f32) of the residual, which is
+// exact in FP32.  The first two terms of the three-term split are the
+// two-term split.
+template <int NP>
+__device__ __forceinline__ void split_bf16n(float x, unsigned short (&o)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const __bf16 h = (__bf16)x;
+        o[i] = __builtin_bit_cast(unsigned short, h);
+        x -= (float)h;
+    }
 }
 
 template <class T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
@@ -325,18 +335,31 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(KRef<GemmArgs> r) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 kernel: FP32 operands split into hi/lo BF16 in LDS, tiles As[m][k], Bs[n][k]
-// PLANES: output split into bf16 hi/lo planes (see GemmArgs), else FP32.
-template <bool AK, int NT, bool PLANES>
+// Split-BF16 kernel: FP32 operands split into NP bf16 planes in LDS, tiles
+// As[m][k], Bs[n][k]; NP = 2 (BF16x3) or 3 (BF16x6).
+// PLANES: output split into NP bf16 planes (see GemmArgs), else FP32.
+template <int NP>
+__device__ __forceinline__ v4f mma_split(const v8bf (&a)[NP], const v8bf (&b)[NP], v4f acc) {
+    // smallest terms first
+    if constexpr (NP == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+    return acc;
+}
+
+template <bool AK, int NT, bool PLANES, int NP>
 __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
     constexpr int BK = 32;
     constexpr int BN = 16 * NT;
     constexpr int SK = BK + 8;       // padded k stride (bf16 elements)
 
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][SK];
-    __shared__ __attribute__((aligned(16))) unsigned short Al[BM][SK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][SK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bl[BN][SK];
+    __shared__ __attribute__((aligned(16))) unsigned short As[NP][BM][SK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[NP][BN][SK];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -404,32 +427,34 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
     auto store_chunk = [&]() {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            v8us hi, lo;
+            v8us t[NP];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                unsigned short a, b;
-                split_bf16(ra[h * 8 + e], a, b);
-                hi[e] = a;
-                lo[e] = b;
+                unsigned short o[NP];
+                split_bf16n<NP>(ra[h * 8 + e], o);
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) t[pl][e] = o[pl];
             }
-            *reinterpret_cast<v8us *>(&Ah[a_m][a_k0 + h * 8]) = hi;
-            *reinterpret_cast<v8us *>(&Al[a_m][a_k0 + h * 8]) = lo;
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl)
+                *reinterpret_cast<v8us *>(&As[pl][a_m][a_k0 + h * 8]) = t[pl];
         }
 #pragma unroll
         for (int it = 0; it < B_ITERS; ++it) {
             const int grp = tid + it * NTHREADS;
             if (grp < BG) {
                 const int n = grp % BN, kg = grp / BN;
-                v8us hi, lo;
+                v8us t[NP];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    unsigned short a, b;
-                    split_bf16(rb[it][e], a, b);
-                    hi[e] = a;
-                    lo[e] = b;
+                    unsigned short o[NP];
+                    split_bf16n<NP>(rb[it][e], o);
+#pragma unroll
+                    for (int pl = 0; pl < NP; ++pl) t[pl][e] = o[pl];
                 }
-                *reinterpret_cast<v8us *>(&Bh[n][kg * 8]) = hi;
-                *reinterpret_cast<v8us *>(&Bl[n][kg * 8]) = lo;
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl)
+                    *reinterpret_cast<v8us *>(&Bs[pl][n][kg * 8]) = t[pl];
             }
         }
     };
@@ -442,24 +467,23 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
         __syncthreads();
         if (ch + 1 < nchunks) load_chunk((ch + 1) * BK);
         const int kq = (lane >> 4) * 8;
-        v8bf ah[RT], al[RT];
+        v8bf av[RT][NP];
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
             const int m = wave * (16 * RT) + r * 16 + (lane & 15);
-            ah[r] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&Ah[m][kq]));
-            al[r] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&Al[m][kq]));
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl)
+                av[r][pl] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&As[pl][m][kq]));
         }
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int n = c * 16 + (lane & 15);
-            v8bf bh = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&Bh[n][kq]));
-            v8bf bl = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&Bl[n][kq]));
+            v8bf bv[NP];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][c], 0, 0, 0);
-            }
+            for (int pl = 0; pl < NP; ++pl)
+                bv[pl] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v8us *>(&Bs[pl][n][kq]));
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r][c] = mma_split<NP>(av[r], bv, acc[r][c]);
         }
     }
 
@@ -479,12 +503,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
                 if (m < g.M && n < g.N) {
                     const float x = (float)(g.alpha * (double)acc[r][c][e]);
                     if constexpr (PLANES) {
-                        unsigned short hi, lo;
-                        split_bf16(x, hi, lo);
+                        unsigned short o[NP];
+                        split_bf16n<NP>(x, o);
                         unsigned short *C = static_cast<unsigned short *>(g.C);
                         const long long idx = (long long)z * g.sC + m * g.ldc + (long long)pq * g.pld + pk;
-                        C[idx] = hi;
-                        C[idx + g.plane] = lo;
+#pragma unroll
+                        for (int pl = 0; pl < NP; ++pl) C[idx + pl * g.plane] = o[pl];
                     } else {
                         static_cast<float *>(g.C)[(long long)z * g.sC + m * g.ldc + n] = x;
                     }
@@ -501,8 +525,9 @@ template <int MODE, bool AK, bool OUT64, int BK_>
 static void launch_nt(int nt, dim3 grid, hipStream_t s, const KRef<GemmArgs> &r) {
 #define GF2_NT_CASE(T)                                                                      \
     case T:                                                                                 \
-        if constexpr (MODE == MODE_BF3)                                                     \
-            hipLaunchKernelGGL((gemm_bf3<AK, T, OUT64>), grid, dim3(NTHREADS), 0, s, r);    \
+        if constexpr (split_planes(MODE) > 0)                                               \
+            hipLaunchKernelGGL((gemm_bf3<AK, T, OUT64, split_planes(MODE)>), grid,           \
+                               dim3(NTHREADS), 0, s, r);                                    \
         else                                                                                \
             hipLaunchKernelGGL((gemm_fp<MODE, AK, T, OUT64, BK_>), grid, dim3(NTHREADS), 0, s, r); \
         break;
@@ -1164,36 +1189,45 @@ __global__ void k_reduce_split(int n, int nb, int nsplit, const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 forms of S23 and S4.
+// Split-BF16 forms (BF16x3: NP = 2 planes, BF16x6: NP = 3) of S23 and S4.
 //
-// Operands are pre-split into bf16 hi and lo planes where they are produced
-// or staged, so the kernels issue loads and MFMAs only:
-//   T1  hi/lo planes [i][t][n][q][k] with rows padded to LQ = roundup(n, 8)
+// Operands are pre-split into NP bf16 planes where they are produced or
+// staged, so the kernels issue loads and MFMAs only:
+//   T1  planes [i][t][n][q][k] with rows padded to LQ = roundup(n, 8)
 //       (written by the first transform; padding is zero);
-//   Gq  hi/lo planes of G(tau) [t][l][col] for the third transform, col in
-//       the K order of a 32-deep MFMA fed by two FP32 result tiles (below);
-//   W2b hi/lo planes of W2 [k / 64][j][64] with k in the K order of the A
-//       operand of the final contraction (below), built once per system.
+//   Gq  planes of G(tau) [t][l][col] for the third transform, col in the K
+//       order of a 32-deep MFMA fed by two FP32 result tiles (below);
+//   W2b planes of W2 [k / 64][j][64] with k in the K order of the A operand
+//       of the final contraction (below), built once per system with three
+//       planes (the two-term forms read the first two).
 // v_mfma_f32_16x16x32_bf16: lane (a = lane/16, c = lane%16) holds A[c][8a..8a+7]
 // and B[8a..8a+7][c]; the result tile is laid out like the FP32 MFMA's.
 typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ v8bf_t as_bf8(v8us x) { return __builtin_bit_cast(v8bf_t, x); }
 
-__device__ __forceinline__ void split8(const float (&x)[8], v8us &hi, v8us &lo) {
+template <int NP>
+__device__ __forceinline__ void split8(const float (&x)[8], v8us (&o)[NP]) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        unsigned short h, l;
-        split_bf16(x[e], h, l);
-        hi[e] = h;
-        lo[e] = l;
+        unsigned short t[NP];
+        split_bf16n<NP>(x[e], t);
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl) o[pl][e] = t[pl];
     }
 }
 
-__device__ __forceinline__ v4f mma3(v8us ah, v8us al, v8us bh, v8us bl, v4f acc) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bl), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al), as_bf8(bh), acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bh), acc, 0, 0, 0);
+template <int NP>
+__device__ __forceinline__ v4f mma3(const v8us (&a)[NP], const v8us (&b)[NP], v4f acc) {
+    // same products and order as mma_split
+    if constexpr (NP == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[1]), as_bf8(b[1]), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[0]), as_bf8(b[2]), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[2]), as_bf8(b[0]), acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[0]), as_bf8(b[1]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[1]), as_bf8(b[0]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[0]), as_bf8(b[0]), acc, 0, 0, 0);
     return acc;
 }
 
@@ -1205,8 +1239,9 @@ __device__ __forceinline__ int pair_row(int slot) {
     return (j < 4) ? 4 * a + j : 16 + 4 * a + (j - 4);
 }
 
-// Gq[t][l][col], col < 32 * KP: G(tau_{k0+t})[l][k], k = 32 (col / 32) + pair_row(col % 32)
-__global__ void k_stage_gq(int n, int KP, int sl, int p16, int k0, int nb, size_t plane,
+// Gq[t][l][col], col < 32 * KP: G(tau_{k0+t})[l][k], k = 32 (col / 32) + pair_row(col % 32);
+// np planes (2 or 3)
+__global__ void k_stage_gq(int n, int KP, int sl, int p16, int k0, int nb, size_t plane, int np,
                            const double *__restrict__ Gt, unsigned short *__restrict__ Gq) {
     const size_t per = (size_t)p16 * sl;
     const size_t n2 = (size_t)n * n;
@@ -1219,25 +1254,26 @@ __global__ void k_stage_gq(int n, int KP, int sl, int p16, int k0, int nb, size_
         const int k = 32 * (col >> 5) + pair_row(col & 31);
         float x = 0.0f;
         if (col < 32 * KP && l < n && k < n) x = (float)Gt[(size_t)(k0 + t) * n2 + (size_t)l * n + k];
-        unsigned short h, lo;
-        split_bf16(x, h, lo);
-        Gq[idx] = h;
-        Gq[idx + plane] = lo;
+        unsigned short o[3];
+        split_bf16n<3>(x, o);
+        Gq[idx] = o[0];
+        Gq[idx + plane] = o[1];
+        if (np == 3) Gq[idx + 2 * plane] = o[2];
     }
 }
 
 struct S23b3Args {
-    const unsigned short *T1;   // hi plane; lo plane at + t1_plane
+    const unsigned short *T1;   // plane 0; plane i at + i * t1_plane
     long long t1_plane;
     int lq;                     // padded slab row
-    const unsigned short *Gq;   // hi plane; lo plane at + gq_plane
+    const unsigned short *Gq;   // plane 0; plane i at + i * gq_plane
     long long gq_plane;
     const float *Gb;            // G(-tau) [nb][n][n] FP32
     float *X;                   // [n][n][R][n] FP32
     int n, nb;
 };
 
-template <int KT>
+template <int KT, int NP>
 __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     constexpr int KP = (KT + 1) / 2;          // 32-deep k steps of the second product
     constexpr int P16 = 16 * KT;
@@ -1254,30 +1290,27 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     const int S32 = (N + 31) >> 5;            // 32-deep q steps of the first product
     const int SQ = 32 * S32 + 8;              // LDS row of the G(-tau) slice (bf16)
 
-    unsigned short *GH = reinterpret_cast<unsigned short *>(s23b_smem);
-    unsigned short *GL = GH + P16 * SLG;
-    unsigned short *BH = GL + P16 * SLG;      // [16][SQ]: G(-tau)[q][16 pt + c] at [c][q]
-    unsigned short *BL = BH + 16 * SQ;
+    // NP planes of the Gq slice, then NP planes of [16][SQ]: G(-tau)[q][16 pt + c] at [c][q]
+    unsigned short *GS = reinterpret_cast<unsigned short *>(s23b_smem);
+    unsigned short *BS = GS + NP * P16 * SLG;
     const int tid = threadIdx.x, nth = blockDim.x;
     {
         const size_t off = (size_t)t * P16 * SLG;
         const int n16 = P16 * SLG / 8;
-        const float4 *sh = reinterpret_cast<const float4 *>(a.Gq + off);
-        const float4 *sl = reinterpret_cast<const float4 *>(a.Gq + a.gq_plane + off);
-        float4 *dh = reinterpret_cast<float4 *>(GH);
-        float4 *dl = reinterpret_cast<float4 *>(GL);
-        for (int e = tid; e < n16; e += nth) {
-            dh[e] = sh[e];
-            dl[e] = sl[e];
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl) {
+            const float4 *src = reinterpret_cast<const float4 *>(a.Gq + pl * a.gq_plane + off);
+            float4 *dst = reinterpret_cast<float4 *>(GS + pl * P16 * SLG);
+            for (int e = tid; e < n16; e += nth) dst[e] = src[e];
         }
         const float *Gb = a.Gb + (size_t)t * N * N;
         for (int e = tid; e < 16 * SQ; e += nth) {
             const int cc = e / SQ, q = e - cc * SQ, p = 16 * pt + cc;
             const float x = (q < N && p < N) ? Gb[(size_t)q * N + p] : 0.0f;
-            unsigned short h, l;
-            split_bf16(x, h, l);
-            BH[e] = h;
-            BL[e] = l;
+            unsigned short o[NP];
+            split_bf16n<NP>(x, o);
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) BS[pl * 16 * SQ + e] = o[pl];
         }
     }
     __syncthreads();
@@ -1291,8 +1324,15 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     // rows k >= N read row N - 1 (finite; they meet zero rows of G); q
     // blocks past the padded row read q = 0 (they meet zero rows of G(-tau))
     const int kc_last = min(16 * (KT - 1) + c, N - 1);
-    const unsigned short *T1h = a.T1;
-    const unsigned short *T1l = a.T1 + a.t1_plane;
+    const unsigned short *T1p[NP];
+    const unsigned short *GSp[NP];
+    const unsigned short *BSp[NP];
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl) {
+        T1p[pl] = a.T1 + pl * a.t1_plane;
+        GSp[pl] = GS + pl * P16 * SLG;
+        BSp[pl] = BS + pl * 16 * SQ + c * SQ + 8 * g;
+    }
 
     for (int i = tid >> 6; i < N; i += nw) {
         const size_t soff = (((size_t)i * a.nb + t) * N + nn) * slab_sz;
@@ -1301,7 +1341,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
         for (int kt = 0; kt < 2 * KP; ++kt) acc1[kt] = v4f{0, 0, 0, 0};
 
         // ---- Y^T[k][p] = sum_q T1[k][q] Gb[q][p]  (slab symmetric)
-        v8us ah[KT], al[KT];
+        v8us av[KT][NP];
         auto load = [&](int s) {
             int q0 = 32 * s + 8 * g;
             if (q0 + 8 > a.lq) q0 = 0;
@@ -1309,27 +1349,45 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
             for (int kt = 0; kt < KT; ++kt) {
                 const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
                 const size_t o = soff + (size_t)k * a.lq + q0;
-                ah[kt] = *reinterpret_cast<const v8us *>(T1h + o);
-                al[kt] = *reinterpret_cast<const v8us *>(T1l + o);
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *reinterpret_cast<const v8us *>(T1p[pl] + o);
             }
         };
         load(0);
         for (int s = 0; s < S32; ++s) {
-            const v8us bh = *reinterpret_cast<const v8us *>(BH + c * SQ + 32 * s + 8 * g);
-            const v8us bl = *reinterpret_cast<const v8us *>(BL + c * SQ + 32 * s + 8 * g);
-            v8us ch[KT], cl[KT];
+            v8us bv[NP];
 #pragma unroll
-            for (int kt = 0; kt < KT; ++kt) {
-                ch[kt] = ah[kt];
-                cl[kt] = al[kt];
+            for (int pl = 0; pl < NP; ++pl) bv[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 32 * s);
+            if constexpr (NP == 2) {
+                // whole next step prefetched into a second register set
+                v8us cv[KT][NP];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                    for (int pl = 0; pl < NP; ++pl) cv[kt][pl] = av[kt][pl];
+                if (s + 1 < S32) load(s + 1);
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) acc1[kt] = mma3<NP>(cv[kt], bv, acc1[kt]);
+            } else {
+                // three planes: no room for a second set; each k tile's next
+                // operands are loaded into its registers once its products issue
+                int q1 = 32 * (s + 1) + 8 * g;
+                if (q1 + 8 > a.lq) q1 = 0;
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) {
+                    acc1[kt] = mma3<NP>(av[kt], bv, acc1[kt]);
+                    if (s + 1 < S32) {
+                        const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
+                        const size_t o = soff + (size_t)k * a.lq + q1;
+#pragma unroll
+                        for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *reinterpret_cast<const v8us *>(T1p[pl] + o);
+                    }
+                }
             }
-            if (s + 1 < S32) load(s + 1);
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt) acc1[kt] = mma3(ch[kt], cl[kt], bh, bl, acc1[kt]);
         }
 
         // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p]; B operand = two result tiles
-        v8us yh[KP], yl[KP];
+        v8us yv[KP][NP];
 #pragma unroll
         for (int u = 0; u < KP; ++u) {
             float y[8];
@@ -1338,7 +1396,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
                 y[e] = acc1[2 * u][e];
                 y[4 + e] = acc1[2 * u + 1][e];
             }
-            split8(y, yh[u], yl[u]);
+            split8<NP>(y, yv[u]);
         }
         float *xbase = a.X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
 #pragma unroll 1
@@ -1347,9 +1405,10 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
             const int row = (16 * lt + c) * SLG + 8 * g;
 #pragma unroll
             for (int u = 0; u < KP; ++u) {
-                const v8us gh = *reinterpret_cast<const v8us *>(GH + row + 32 * u);
-                const v8us gl = *reinterpret_cast<const v8us *>(GL + row + 32 * u);
-                acc2 = mma3(gh, gl, yh[u], yl[u], acc2);
+                v8us gv[NP];
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) gv[pl] = *reinterpret_cast<const v8us *>(GSp[pl] + row + 32 * u);
+                acc2 = mma3<NP>(gv, yv[u], acc2);
             }
             if (p < N) {
                 const int l0 = 16 * lt + 4 * g;
@@ -1365,7 +1424,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     }
 }
 
-// W2b[kc][j][w] (hi; lo at + plane), w < 64: W2[k][j] with
+// W2b[kc][j][w] (three planes, plane i at + i * plane), w < 64: W2[k][j] with
 // k = 64 kc + 32 (w / 32) + pair_row(w % 32); zero for k >= n^3 or j >= n.
 __global__ void k_build_w2b(int n, int bn, long long nkc, size_t plane, const double *__restrict__ v,
                             unsigned short *__restrict__ W2b) {
@@ -1383,27 +1442,28 @@ __global__ void k_build_w2b(int n, int bn, long long nkc, size_t plane, const do
             const size_t nn = k / n2, pp = (k / n) % n, l = k % n;
             x = (float)(2.0 * v[((l * n + pp) * n + nn) * n + j] - v[((nn * n + pp) * n + l) * n + j]);
         }
-        unsigned short h, lo;
-        split_bf16(x, h, lo);
-        W2b[idx] = h;
-        W2b[idx + plane] = lo;
+        unsigned short o[3];
+        split_bf16n<3>(x, o);
+        W2b[idx] = o[0];
+        W2b[idx + plane] = o[1];
+        W2b[idx + 2 * plane] = o[2];
     }
 }
 
-// Final contraction in BF16x3.  Each wave owns 16 rows and reads its A
+// Final contraction in split BF16.  Each wave owns 16 rows and reads its A
 // operand (X, FP32) straight from memory, splitting it in registers; the W2b
 // chunk (shared by the 8 waves) goes through LDS.  K order within a 32-deep
 // step: slot 8a + j <-> k = pair_row(8a + j), i.e. two runs of 4 consecutive k.
 struct S4b3Args {
     const float *X;
-    const unsigned short *W2b;   // hi; lo at + plane
+    const unsigned short *W2b;   // plane i at + i * plane
     long long plane;
     double *part;
     long long K, kz;
     int n, R, nrb, nsplit, vec;
 };
 
-template <int NT>
+template <int NT, int NP>
 __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
     constexpr int BK = 64;
     constexpr int BN = 16 * NT;
@@ -1411,8 +1471,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
     constexpr int FLUSH = 512 / BK;
     constexpr int B16 = BN * BK / 8;                  // 16-B units per plane per chunk
     constexpr int B_IT = (B16 + S4_THREADS - 1) / S4_THREADS;
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][SKB];
-    __shared__ __attribute__((aligned(16))) unsigned short Bl[BN][SKB];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[NP][BN][SKB];
 
     S4b3Args a;
     int L;
@@ -1461,7 +1520,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             }
         }
     };
-    v8us rbh[B_IT], rbl[B_IT];
+    v8us rbv[B_IT][NP];
     auto load_b = [&](long long kb) {
         const size_t base = (size_t)(kb / BK) * BN * BK;
 #pragma unroll
@@ -1469,8 +1528,9 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             // threads past the chunk reload its last unit (not stored): no
             // conditional writes, which would put the staging arrays in scratch
             const int u = min(tid + j * S4_THREADS, B16 - 1);
-            rbh[j] = *reinterpret_cast<const v8us *>(a.W2b + base + (size_t)u * 8);
-            rbl[j] = *reinterpret_cast<const v8us *>(a.W2b + a.plane + base + (size_t)u * 8);
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl)
+                rbv[j][pl] = *reinterpret_cast<const v8us *>(a.W2b + pl * a.plane + base + (size_t)u * 8);
         }
     };
     auto store_b = [&]() {
@@ -1479,8 +1539,8 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             // (clamped threads rewrite the last unit with the value it already has)
             const int u = min(tid + j * S4_THREADS, B16 - 1);
             const int jn = u / (BK / 8), w8 = u % (BK / 8);
-            *reinterpret_cast<v8us *>(&Bh[jn][8 * w8]) = rbh[j];
-            *reinterpret_cast<v8us *>(&Bl[jn][8 * w8]) = rbl[j];
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) *reinterpret_cast<v8us *>(&Bs[pl][jn][8 * w8]) = rbv[j][pl];
         }
     };
 
@@ -1502,13 +1562,15 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
         for (int s = 0; s < 2; ++s) {
             float x[8] = {cur[2 * s][0], cur[2 * s][1], cur[2 * s][2], cur[2 * s][3],
                           cur[2 * s + 1][0], cur[2 * s + 1][1], cur[2 * s + 1][2], cur[2 * s + 1][3]};
-            v8us xh, xl;
-            split8(x, xh, xl);
+            v8us xv[NP];
+            split8<NP>(x, xv);
 #pragma unroll
             for (int cc = 0; cc < NT; ++cc) {
-                const v8us bh = *reinterpret_cast<const v8us *>(&Bh[16 * cc + c][32 * s + 8 * g]);
-                const v8us bl = *reinterpret_cast<const v8us *>(&Bl[16 * cc + c][32 * s + 8 * g]);
-                acc[cc] = mma3(xh, xl, bh, bl, acc[cc]);
+                v8us bv[NP];
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl)
+                    bv[pl] = *reinterpret_cast<const v8us *>(&Bs[pl][16 * cc + c][32 * s + 8 * g]);
+                acc[cc] = mma3<NP>(xv, bv, acc[cc]);
             }
         }
         if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
@@ -1625,30 +1687,34 @@ static int launch_s4(hipStream_t st, int nt, dim3 grid, const KRef<S4Args> &r) {
     return GF2_OK;
 }
 
+// Largest column-tile count of the split forms: BF16x3 runs n <= 160, BF16x6
+// (three planes of the G slices in LDS) n <= 144.
+static int split_max_kt(int np) { return np == 3 ? 9 : 10; }
+
 template <int KT>
-static size_t s23b3_lds(int n) {
+static size_t s23b3_lds(int n, int np) {
     constexpr int KP = (KT + 1) / 2;
     constexpr int P16 = 16 * KT;
     constexpr int SLG = 32 * KP + 8;
     const int SQ = 32 * ((n + 31) / 32) + 8;
-    return 2 * ((size_t)2 * P16 * SLG + (size_t)2 * 16 * SQ);
+    return 2 * (size_t)np * ((size_t)P16 * SLG + (size_t)16 * SQ);
 }
 
-template <int KT>
+template <int KT, int NP>
 static int launch_s23_bf3_kt(hipStream_t st, dim3 grid, int waves, size_t lds,
                              const KRef<S23b3Args> &r, bool attr_only) {
-    GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT>,
+    GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT, NP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)s23b3_lds<KT>(16 * KT)));
+                                (int)s23b3_lds<KT>(16 * KT, NP)));
     if (attr_only) return GF2_OK;
-    hipLaunchKernelGGL((k_s23_bf3<KT>), grid, dim3(64 * std::min(waves, 8)), lds, st, r);
+    hipLaunchKernelGGL((k_s23_bf3<KT, NP>), grid, dim3(64 * std::min(waves, 8)), lds, st, r);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
-static size_t s23_bf3_lds(int kt, int n) {
+static size_t s23_bf3_lds(int kt, int n, int np) {
     switch (kt) {
-#define GF2_L_CASE(K_) case K_: return s23b3_lds<K_>(n);
+#define GF2_L_CASE(K_) case K_: return s23b3_lds<K_>(n, np);
         GF2_L_CASE(1) GF2_L_CASE(2) GF2_L_CASE(3) GF2_L_CASE(4) GF2_L_CASE(5)
         GF2_L_CASE(6) GF2_L_CASE(7) GF2_L_CASE(8) GF2_L_CASE(9) GF2_L_CASE(10)
 #undef GF2_L_CASE
@@ -1656,36 +1722,60 @@ static size_t s23_bf3_lds(int kt, int n) {
     }
 }
 
-static int launch_s23_bf3(hipStream_t st, int kt, dim3 grid, int waves, size_t lds,
+static int launch_s23_bf3(hipStream_t st, int np, int kt, dim3 grid, int waves, size_t lds,
                           const KRef<S23b3Args> &r, bool attr_only = false) {
-    switch (kt) {
-#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_>(st, grid, waves, lds, r, attr_only);
-        GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
-        GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9) GF2_B_CASE(10)
+    if (kt > split_max_kt(np)) return fail(GF2_EINVAL, "gf2_sigma_tau: n too large for this precision");
+    if (np == 3) {
+        switch (kt) {
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 3>(st, grid, waves, lds, r, attr_only);
+            GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
+            GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9)
 #undef GF2_B_CASE
-        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+            default: break;
+        }
+    } else {
+        switch (kt) {
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 2>(st, grid, waves, lds, r, attr_only);
+            GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
+            GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9) GF2_B_CASE(10)
+#undef GF2_B_CASE
+            default: break;
+        }
     }
+    return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
 }
 
-static int launch_s4_bf3(hipStream_t st, int nt, dim3 grid, const KRef<S4b3Args> &r) {
-    switch (nt) {
-#define GF2_S4B_CASE(T_) case T_: hipLaunchKernelGGL((k_s4_bf3<T_>), grid, dim3(S4_THREADS), 0, st, r); break;
-        GF2_S4B_CASE(1) GF2_S4B_CASE(2) GF2_S4B_CASE(3) GF2_S4B_CASE(4) GF2_S4B_CASE(5)
-        GF2_S4B_CASE(6) GF2_S4B_CASE(7) GF2_S4B_CASE(8) GF2_S4B_CASE(9) GF2_S4B_CASE(10)
+static int launch_s4_bf3(hipStream_t st, int np, int nt, dim3 grid, const KRef<S4b3Args> &r) {
+    if (nt > split_max_kt(np)) return fail(GF2_EINVAL, "gf2_sigma_tau: n too large for this precision");
+    if (np == 3) {
+        switch (nt) {
+#define GF2_S4B_CASE(T_) case T_: hipLaunchKernelGGL((k_s4_bf3<T_, 3>), grid, dim3(S4_THREADS), 0, st, r); break;
+            GF2_S4B_CASE(1) GF2_S4B_CASE(2) GF2_S4B_CASE(3) GF2_S4B_CASE(4) GF2_S4B_CASE(5)
+            GF2_S4B_CASE(6) GF2_S4B_CASE(7) GF2_S4B_CASE(8) GF2_S4B_CASE(9)
 #undef GF2_S4B_CASE
-        default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+            default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+        }
+    } else {
+        switch (nt) {
+#define GF2_S4B_CASE(T_) case T_: hipLaunchKernelGGL((k_s4_bf3<T_, 2>), grid, dim3(S4_THREADS), 0, st, r); break;
+            GF2_S4B_CASE(1) GF2_S4B_CASE(2) GF2_S4B_CASE(3) GF2_S4B_CASE(4) GF2_S4B_CASE(5)
+            GF2_S4B_CASE(6) GF2_S4B_CASE(7) GF2_S4B_CASE(8) GF2_S4B_CASE(9) GF2_S4B_CASE(10)
+#undef GF2_S4B_CASE
+            default: return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+        }
     }
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 
-// W2 planes for the BF16x3 final contraction (once per system)
+// W2 planes for the split-BF16 final contraction (once per system; three
+// planes, of which BF16x3 reads the first two)
 static int build_bf3_layouts(gf2_ctx *c) {
     const long long n = c->n, n3 = n * n * n;
     const int bn = 16 * (int)((n + 15) / 16);
     const long long nkc = (n3 + 63) / 64;
     const size_t plane = (size_t)nkc * bn * 64;
-    GF2_TRY(c->W2_b3.ensure(2 * plane * 2));
+    GF2_TRY(c->W2_b3.ensure(3 * plane * 2));
     const unsigned blocks = (unsigned)std::min<size_t>((plane + 255) / 256, 65536);
     hipLaunchKernelGGL(k_build_w2b, dim3(blocks), dim3(256), 0, c->stream, (int)n, bn, nkc, plane,
                        c->v.as<double>(), c->W2_b3.as<unsigned short>());
@@ -1720,15 +1810,19 @@ struct SigPlan {
 
 static int sigma_bmax(int n, int mode) {
     const size_t esz = (mode == MODE_F64) ? 8 : 4;
+    const size_t t1sz = split_planes(mode) ? 2 * (size_t)split_planes(mode) : esz;
     const size_t N4 = (size_t)n * n * n * n;
     const size_t budget = (size_t)16 << 30;   // T1 + X
-    return (int)std::min<size_t>(std::max<size_t>(1, budget / (2 * N4 * esz)), 64);
+    return (int)std::min<size_t>(std::max<size_t>(1, budget / (N4 * (esz + t1sz))), 64);
 }
 
 static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape sh,
                      SigPlan &p) {
     const int n = c->n;
     if (n > 160) return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
+    const int np = split_planes(prec);
+    if (np && (n + 15) / 16 > split_max_kt(np))
+        return fail(GF2_EINVAL, "gf2_sigma_tau: BF16x6 supports n <= 144");
     p = SigPlan();
     p.c = c;
     p.mode = prec;
@@ -1740,7 +1834,7 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
     const long long N = n, N2 = N * N, N3 = N2 * N, N4 = N3 * N;
     const size_t esz = (p.mode == MODE_F64) ? 8 : 4;
     if (p.mode != MODE_F64 && !c->have_f32_layouts) GF2_TRY(sigma_build_layouts(c, true));
-    if (p.mode == MODE_BF3 && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
+    if (np && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
     p.V = (p.mode == MODE_F64) ? c->v.ptr : c->v_32.ptr;
     p.W2 = (p.mode == MODE_F64) ? c->W2_64.ptr : c->W2_32.ptr;
     p.KT = (n + 15) / 16;
@@ -1758,21 +1852,21 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
                      : (p.mode == MODE_F32) ? max_waves<MODE_F32>(p.KT) : 8;
     if (sh.waves > 0) {
         p.sh.waves = std::min(sh.waves, wmax);
-    } else if (p.mode == MODE_BF3) {
-        const int per_cu = std::max<int>(1, (int)((160 * 1024) / s23_bf3_lds(p.KT, n)));
+    } else if (np) {
+        const int per_cu = std::max<int>(1, (int)((160 * 1024) / s23_bf3_lds(p.KT, n, np)));
         p.sh.waves = std::min(8, std::max(4, 16 / per_cu));
     } else {
         p.sh.waves = (p.mode == MODE_F64) ? default_waves<MODE_F64>(p.KT, n)
                                           : default_waves<MODE_F32>(p.KT, n);
     }
-    p.sh.s4cb = (p.mode == MODE_BF3) ? 1 : (sh.s4cb > 0 ? std::min(sh.s4cb, 2) : 1);
+    p.sh.s4cb = np ? 1 : (sh.s4cb > 0 ? std::min(sh.s4cb, 2) : 1);
     p.s4_nt = (p.KT + p.sh.s4cb - 1) / p.sh.s4cb;
     const size_t b = (size_t)p.sh.b;
     p.t1_plane = b * N2 * N * p.lq;
     p.gq_plane = b * 16 * p.KT * p.SLG;
-    if (p.mode == MODE_BF3) {
-        GF2_TRY(c->sig_T1.ensure(2 * p.t1_plane * 2));
-        GF2_TRY(c->sig_Gq.ensure(2 * p.gq_plane * 2));
+    if (np) {
+        GF2_TRY(c->sig_T1.ensure(np * p.t1_plane * 2));
+        GF2_TRY(c->sig_Gq.ensure(np * p.gq_plane * 2));
     }
     GF2_TRY(c->sig_T1.ensure(b * N4 * esz));
     GF2_TRY(c->sig_X.ensure(b * N4 * esz));
@@ -1807,7 +1901,8 @@ static int plan_stage(const SigPlan &p, hipStream_t st, int k0, int nb) {
             const size_t totq = (size_t)nb * 16 * p.KT * p.SLG;
             const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
             hipLaunchKernelGGL(k_stage_gq, dim3(blocksq), dim3(256), 0, st, n, p.KP, p.SLG, 16 * p.KT,
-                               k0, nb, p.gq_plane, p.G, c->sig_Gq.as<unsigned short>());
+                               k0, nb, p.gq_plane, split_planes(p.mode), p.G,
+                               c->sig_Gq.as<unsigned short>());
         }
     }
     GF2_HIP(hipGetLastError());
@@ -1834,7 +1929,7 @@ static GemmArgs plan_s1(const SigPlan &p, int nb, int &nt) {
     g.M = (int)R; g.N = (int)N2; g.K = p.n; g.kz = p.n; g.split = 0;
     g.alpha = 1.0;
     g.vecA = 0;
-    if (p.mode == MODE_BF3) {
+    if (split_planes(p.mode)) {
         g.vecA = (p.n % 4 == 0) ? 1 : 0;
         g.pn = p.n;
         g.pld = p.lq;
@@ -1906,6 +2001,7 @@ static S4b3Args plan_s4b3(const SigPlan &p, int nb) {
 static int launch_s1(int mode, int bk, int nt, dim3 grid, hipStream_t st, const KRef<GemmArgs> &r) {
     if (mode == MODE_F64) launch_nt<MODE_F64, false, true, 16>(nt, grid, st, r);
     else if (mode == MODE_BF3) launch_nt<MODE_BF3, false, true, 0>(nt, grid, st, r);
+    else if (mode == MODE_BF6) launch_nt<MODE_BF6, false, true, 0>(nt, grid, st, r);
     else if (bk == 20) launch_nt<MODE_F32, false, false, 20>(nt, grid, st, r);
     else launch_nt<MODE_F32, false, false, 16>(nt, grid, st, r);
     GF2_HIP(hipGetLastError());
@@ -1927,13 +2023,14 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
         if (prof) prof_end(c, ph, fl);
     }
     {
-        const int groups = (p.mode == MODE_BF3) ? p.KT : s23_groups(p.mode, p.KT);
+        const int np = split_planes(p.mode);
+        const int groups = np ? p.KT : s23_groups(p.mode, p.KT);
         const dim3 grid(xcd_grid((long long)nb * p.n * groups));
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_S23) : -1;
-        if (p.mode == MODE_BF3) {
+        if (np) {
             KRef<S23b3Args> r{};
             r.one = plan_s23b3(p, nb);
-            GF2_TRY(launch_s23_bf3(st, p.KT, grid, p.sh.waves, s23_bf3_lds(p.KT, p.n), r));
+            GF2_TRY(launch_s23_bf3(st, np, p.KT, grid, p.sh.waves, s23_bf3_lds(p.KT, p.n, np), r));
         } else {
             KRef<S23Args> r{};
             r.one = plan_s23(p, nb);
@@ -1946,11 +2043,11 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
     }
     {
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_SPLITK) : -1;
-        if (p.mode == MODE_BF3) {
+        if (split_planes(p.mode)) {
             KRef<S4b3Args> r{};
             r.one = plan_s4b3(p, nb);
             const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit));
-            GF2_TRY(launch_s4_bf3(st, p.KT, grid, r));
+            GF2_TRY(launch_s4_bf3(st, split_planes(p.mode), p.KT, grid, r));
         } else {
             KRef<S4Args> r{};
             r.one = plan_s4(p, nb);
@@ -1964,8 +2061,8 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
 }
 
 static int plan_run(SigPlan &p, bool prof) {
-    if (p.mode == MODE_BF3)   // the first transform never writes the padding of the T1 rows
-        GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, 2 * p.t1_plane * 2));
+    if (split_planes(p.mode))   // the first transform never writes the padding of the T1 rows
+        GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, split_planes(p.mode) * p.t1_plane * 2));
     for (int k0 = 0; k0 < p.ntau; k0 += p.sh.b)
         GF2_TRY(plan_run_batch(p, p.c->stream, k0, std::min(p.sh.b, p.ntau - k0), prof));
     return GF2_OK;
@@ -2012,13 +2109,13 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
         std::vector<int> bs;
         for (int b : {bmax, (bmax + 1) / 2, (bmax + 3) / 4})
             if (b >= 1 && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
-        std::vector<int> ws = (prec == MODE_BF3) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+        std::vector<int> ws = split_planes(prec) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
         hipEvent_t e0, e1;
         GF2_HIP(hipEventCreate(&e0));
         GF2_HIP(hipEventCreate(&e1));
         double best_t = 1e300;
         int rc = GF2_OK;
-        std::vector<int> cbs = (prec == MODE_BF3) ? std::vector<int>{1} : std::vector<int>{1, 2};
+        std::vector<int> cbs = split_planes(prec) ? std::vector<int>{1} : std::vector<int>{1, 2};
         for (int b : bs) {
           for (int cb : cbs) {
             for (int w : ws) {
@@ -2026,7 +2123,7 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
                 rc = plan_init(c, ntau, prec, G, Sig, SigShape{b, w, cb}, p);
                 if (rc != GF2_OK) break;
                 if (p.sh.waves != w || p.sh.s4cb != cb) continue;   // not a distinct shape
-                if (prec == MODE_BF3) rc = fill_zero(c, c->sig_T1.ptr, 2 * p.t1_plane * 2);
+                if (split_planes(prec)) rc = fill_zero(c, c->sig_T1.ptr, split_planes(prec) * p.t1_plane * 2);
                 if (rc != GF2_OK) break;
                 const int nb = std::min(b, ntau);
                 (void)hipEventRecord(e0, c->stream);
@@ -2102,8 +2199,9 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
         GF2_TRY(tuned_shape(cs[s], ntau[s], prec, G[s], Sig[s], sh));
         GF2_TRY(plan_init(cs[s], ntau[s], prec, G[s], Sig[s], sh, plans[s]));
     }
-    if (prec == MODE_BF3)
-        for (auto &p : plans) GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, 2 * p.t1_plane * 2));
+    const int np = split_planes(prec);
+    if (np)
+        for (auto &p : plans) GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, np * p.t1_plane * 2));
     // shape key: everything the captured launches depend on
     long long key = 1469598103934665603LL ^ prec;
     auto mix = [&](long long v) { key = (key ^ v) * 1099511628211LL; };
@@ -2160,12 +2258,12 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
             std::vector<int> boff{0};
             size_t lds = 0;
             GroupLaunch gl{2, kv.first.first, kv.first.second, 0, 0, 0, (int)kv.second.size(), 0, 0};
-            if (prec == MODE_BF3) {
+            if (np) {
                 std::vector<S23b3Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s23b3(plans[s], nb_of(s)));
                     boff.push_back(boff.back() + nb_of(s) * plans[s].n * plans[s].KT);
-                    lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n));
+                    lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n, np));
                 }
                 push_table(buf, tab, boff, gl);
             } else {
@@ -2184,11 +2282,11 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
         }
         // S4 classes (NT)
         std::map<int, std::vector<int>> c4;
-        for (int s : act) c4[prec == MODE_BF3 ? plans[s].KT : plans[s].s4_nt].push_back(s);
+        for (int s : act) c4[np ? plans[s].KT : plans[s].s4_nt].push_back(s);
         for (auto &kv : c4) {
             std::vector<int> boff{0};
             GroupLaunch gl{4, kv.first, 0, 0, 0, 0, (int)kv.second.size(), 0, 0};
-            if (prec == MODE_BF3) {
+            if (np) {
                 std::vector<S4b3Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s4b3(plans[s], nb_of(s)));
@@ -2216,7 +2314,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
             if (gl.stage == 2) {
                 KRef<S23Args> r0{};
                 KRef<S23b3Args> r1{};
-                if (prec == MODE_BF3) GF2_TRY(launch_s23_bf3(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r1, true));
+                if (np) GF2_TRY(launch_s23_bf3(lead->stream, np, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r1, true));
                 else if (prec == MODE_F64) GF2_TRY(launch_s23<MODE_F64>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
                 else GF2_TRY(launch_s23<MODE_F32>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
             }
@@ -2243,13 +2341,13 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                 ref.total = gl.total;
                 rc = launch_s1(prec, gl.cls_a, gl.cls_b, grid, st, ref);
             } else if (gl.stage == 2) {
-                if (prec == MODE_BF3) {
+                if (np) {
                     KRef<S23b3Args> ref{};
                     ref.tab = reinterpret_cast<const S23b3Args *>(tb + gl.tab_off);
                     ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
                     ref.nsys = gl.nsys;
                     ref.total = gl.total;
-                    rc = launch_s23_bf3(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
+                    rc = launch_s23_bf3(st, np, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
                 } else {
                     KRef<S23Args> ref{};
                     ref.tab = reinterpret_cast<const S23Args *>(tb + gl.tab_off);
@@ -2260,13 +2358,13 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                     else rc = launch_s23<MODE_F32>(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
                 }
             } else {
-                if (prec == MODE_BF3) {
+                if (np) {
                     KRef<S4b3Args> ref{};
                     ref.tab = reinterpret_cast<const S4b3Args *>(tb + gl.tab_off);
                     ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
                     ref.nsys = gl.nsys;
                     ref.total = gl.total;
-                    rc = launch_s4_bf3(st, gl.cls_a, grid, ref);
+                    rc = launch_s4_bf3(st, np, gl.cls_a, grid, ref);
                 } else {
                     KRef<S4Args> ref{};
                     ref.tab = reinterpret_cast<const S4Args *>(tb + gl.tab_off);
@@ -2327,7 +2425,7 @@ extern "C" int gf2_sigma_tau(gf2_ctx *c, const gf2_dims *d, int prec, const doub
     if (!c->has_system) return fail(GF2_ESTATE, "gf2_sigma_tau: no system set");
     if (d->n != c->n) return fail(GF2_EINVAL, "gf2_sigma_tau: dims->n differs from the system");
     if (d->ntau < 4) return fail(GF2_EINVAL, "gf2_sigma_tau: ntau must be >= 4");
-    if (prec < GF2_PREC_FP64 || prec > GF2_PREC_BF16X3)
+    if (prec < GF2_PREC_FP64 || prec > GF2_PREC_BF16X6)
         return fail(GF2_EINVAL, "gf2_sigma_tau: bad precision");
     if ((const void *)G_tau == (const void *)Sigma_tau)
         return fail(GF2_EINVAL, "gf2_sigma_tau: Sigma_tau aliases G_tau");
