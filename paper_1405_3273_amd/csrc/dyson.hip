@@ -147,13 +147,19 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
 
     double acc_tr = 0.0, acc_e = 0.0;
     double mr[RA][CB], mi[RA][CB];
+    const GF2_GLOBAL double *gS = (const GF2_GLOBAL double *)a.S;
+    const GF2_GLOBAL double *gF = (const GF2_GLOBAL double *)a.F;
+    const GF2_GLOBAL double *gM = (const GF2_GLOBAL double *)a.mom;
+    typedef double d2_t __attribute__((ext_vector_type(2)));   // (re, im), as double2
+    GF2_GLOBAL d2_t *gG = (GF2_GLOBAL d2_t *)a.G;
 
     for (int nn = lb; nn < a.niw; nn += nbl) {
         const double w = M_PI * (double)(2 * nn + 1) / a.beta;
-        const double2 *Sig = a.Sig ? a.Sig + (size_t)nn * n * n : nullptr;
+        const GF2_GLOBAL d2_t *Sig =
+            a.Sig ? (const GF2_GLOBAL d2_t *)a.Sig + (size_t)nn * n * n : nullptr;
         // The element addresses do not depend on nn; hiding the bases from the
         // optimiser keeps it from holding the pointers live across the elimination.
-        const double *Sb = a.S, *Fb = a.F;
+        const GF2_GLOBAL double *Sb = gS, *Fb = gF;
         int base = tr * n + tc;
         asm volatile("" : "+s"(Sb), "+s"(Fb), "+v"(base));
         // A = (i w + mu) S - F - Sigma_n
@@ -169,7 +175,7 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                     const double s = Sb[e];
                     double re = a.mu * s - Fb[e], im = w * s;
                     if (Sig) {
-                        const double2 sg = Sig[e];
+                        const d2_t sg = Sig[e];
                         re -= sg.x;
                         im -= sg.y;
                     }
@@ -306,19 +312,19 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                 const int ga = rinv[i], gb = perm[j];
                 const size_t e = (size_t)ga * n + gb;
                 const size_t et = (size_t)gb * n + ga;
-                const double sv = a.S[et];
+                const double sv = gS[et];
                 acc_tr += mr[ia][jb] * sv;
                 if (full) {
-                    const double pv = mr[ia][jb] + a.mom[n * n + e] * iw2;
+                    const double pv = mr[ia][jb] + gM[n * n + e] * iw2;
                     if (pm == 2) {
                         // upper triangle, row-major: (ga, gb), ga <= gb
                         if (ga <= gb) shP[ga * n - ga * (ga - 1) / 2 + (gb - ga)] += pv;
                     } else {
                         Pacc[e] += pv;
                     }
-                    if (a.G) a.G[(size_t)nn * n * n + e] = make_double2(mr[ia][jb], mi[ia][jb]);
+                    if (gG) gG[(size_t)nn * n * n + e] = d2_t{mr[ia][jb], mi[ia][jb]};
                     if (en) {
-                        e_r += mr[ia][jb] * fma(a.mu, sv, -a.F[et]);
+                        e_r += mr[ia][jb] * fma(a.mu, sv, -gF[et]);
                         e_i += mi[ia][jb] * sv;
                     }
                 }

@@ -41,6 +41,13 @@ struct DevBuf {
 
 // Sigma(tau) arithmetic modes (match GF2_PREC_*).
 enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2, MODE_BF6 = 3 };
+// Global-memory pointers in kernels.  Pointers read from argument structs are
+// generic, for which the compiler emits flat loads and stores; flat accesses
+// also count against the LDS wait counter, so every wait for an LDS access
+// would wait for the global loads and stores in flight too.  The hot operand
+// streams are therefore addressed through address-space-1 pointers.
+#define GF2_GLOBAL __attribute__((address_space(1)))
+
 // BF16 planes per FP32 operand of a split-precision mode (0: not split).
 constexpr int split_planes(int mode) { return mode == MODE_BF3 ? 2 : mode == MODE_BF6 ? 3 : 0; }
 

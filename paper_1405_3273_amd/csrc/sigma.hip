@@ -53,6 +53,7 @@ static unsigned xcd_grid(long long total) {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8us __attribute__((ext_vector_type(8)));
 
@@ -183,8 +184,8 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(KRef<GemmArgs> r) {
     const long long mb = (long long)bx * BM;
     const int nb = by * BN;
 
-    const in_t *A = static_cast<const in_t *>(g.A) + (long long)z * g.sA;
-    const in_t *B = static_cast<const in_t *>(g.B) + (long long)z * g.sB;
+    const GF2_GLOBAL in_t *A = (const GF2_GLOBAL in_t *)g.A + (long long)z * g.sA;
+    const GF2_GLOBAL in_t *B = (const GF2_GLOBAL in_t *)g.B + (long long)z * g.sB;
     const int Kz = g.split ? min(g.kz, g.K - z * g.kz) : g.K;
     if (Kz <= 0) return;
 
@@ -211,19 +212,19 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(KRef<GemmArgs> r) {
             const int mm = (tid % (BM / A_PER)) * A_PER;
             const long long gk = kb + kk;
             const long long gm = mb + mm;
-            const in_t *p = A + gk * g.lda + gm;
+            const GF2_GLOBAL in_t *p = A + gk * g.lda + gm;
             if (gk < Kz && gm + A_PER <= g.M && g.vecA) {
                 if constexpr (MODE == MODE_F64) {
 #pragma unroll
                     for (int e = 0; e < A_PER; e += 2) {
-                        double2 t = *reinterpret_cast<const double2 *>(p + e);
+                        const v2d t = *(const GF2_GLOBAL v2d *)(p + e);
                         ra[e] = t.x;
                         ra[e + 1] = t.y;
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < A_PER; e += 4) {
-                        float4 t = *reinterpret_cast<const float4 *>(p + e);
+                        const v4f t = *(const GF2_GLOBAL v4f *)(p + e);
                         ra[e] = t.x; ra[e + 1] = t.y; ra[e + 2] = t.z; ra[e + 3] = t.w;
                     }
                 }
@@ -325,9 +326,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_fp(KRef<GemmArgs> r) {
                         double val;
                         if constexpr (MODE == MODE_F64) val = acc[r][c][e];
                         else val = accd[r][c][e];
-                        static_cast<double *>(g.C)[(long long)z * g.sC + m * g.ldc + n] = g.alpha * val;
+                        ((GF2_GLOBAL double *)g.C)[(long long)z * g.sC + m * g.ldc + n] = g.alpha * val;
                     } else {
-                        static_cast<in_t *>(g.C)[(long long)z * g.sC + m * g.ldc + n] =
+                        ((GF2_GLOBAL in_t *)g.C)[(long long)z * g.sC + m * g.ldc + n] =
                             (in_t)(g.alpha * (double)acc[r][c][e]);
                     }
                 }
@@ -370,8 +371,8 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
     const long long mb = (long long)bx * BM;
     const int nb = by * BN;
 
-    const float *A = static_cast<const float *>(g.A) + (long long)z * g.sA;
-    const float *B = static_cast<const float *>(g.B) + (long long)z * g.sB;
+    const GF2_GLOBAL float *A = (const GF2_GLOBAL float *)g.A + (long long)z * g.sA;
+    const GF2_GLOBAL float *B = (const GF2_GLOBAL float *)g.B + (long long)z * g.sB;
     const int Kz = g.split ? min(g.kz, g.K - z * g.kz) : g.K;
     if (Kz <= 0) return;
 
@@ -400,11 +401,11 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
             }
         } else {
             const long long gk = kb + a_k0;
-            const float *p = A + gm * g.lda + gk;
+            const GF2_GLOBAL float *p = A + gm * g.lda + gk;
             if (gm < g.M && gk + 16 <= Kz && g.vecA) {
 #pragma unroll
                 for (int e = 0; e < 16; e += 4) {
-                    float4 t = *reinterpret_cast<const float4 *>(p + e);
+                    const v4f t = *(const GF2_GLOBAL v4f *)(p + e);
                     ra[e] = t.x; ra[e + 1] = t.y; ra[e + 2] = t.z; ra[e + 3] = t.w;
                 }
             } else {
@@ -505,12 +506,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
                     if constexpr (PLANES) {
                         unsigned short o[NP];
                         split_bf16n<NP>(x, o);
-                        unsigned short *C = static_cast<unsigned short *>(g.C);
+                        GF2_GLOBAL unsigned short *C = (GF2_GLOBAL unsigned short *)g.C;
                         const long long idx = (long long)z * g.sC + m * g.ldc + (long long)pq * g.pld + pk;
 #pragma unroll
                         for (int pl = 0; pl < NP; ++pl) C[idx + pl * g.plane] = o[pl];
                     } else {
-                        static_cast<float *>(g.C)[(long long)z * g.sC + m * g.ldc + n] = x;
+                        ((GF2_GLOBAL float *)g.C)[(long long)z * g.sC + m * g.ldc + n] = x;
                     }
                 }
             }
@@ -773,8 +774,8 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     const int nw = nth >> 6;
     const size_t N2 = (size_t)N * N;
     const size_t R = (size_t)a.nb * N;
-    const T *T1 = static_cast<const T *>(a.T1);
-    T *X = static_cast<T *>(a.X);
+    const GF2_GLOBAL T *T1 = (const GF2_GLOBAL T *)a.T1;
+    GF2_GLOBAL T *X = (GF2_GLOBAL T *)a.X;
     const int p = 16 * pt + c;
     const bool vec4 = (MODE != MODE_F64) && (N % 4 == 0);
 
@@ -800,16 +801,16 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     qv_t gb_[KT];
 #endif
     T ta[KT];                                   // one step of the remaining q
-    auto loadg = [&](qv_t(&r)[KT], const T *slab, int u) {
-        const T *col = slab + 4 * GW * u + GW * g;
+    auto loadg = [&](qv_t(&r)[KT], const GF2_GLOBAL T *slab, int u) {
+        const GF2_GLOBAL T *col = slab + 4 * GW * u + GW * g;
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
-            r[kt] = *reinterpret_cast<const qv_t *>(col + (size_t)k * N);
+            r[kt] = *(const GF2_GLOBAL qv_t *)(col + (size_t)k * N);
         }
     };
-    auto load1 = [&](T(&r)[KT], const T *slab, int st) {
-        const T *row = slab + (size_t)min(4 * st + g, N - 1) * N;
+    auto load1 = [&](T(&r)[KT], const GF2_GLOBAL T *slab, int st) {
+        const GF2_GLOBAL T *row = slab + (size_t)min(4 * st + g, N - 1) * N;
 #pragma unroll
         for (int kt = 0; kt < KT - 1; ++kt) r[kt] = row[16 * kt + c];
         r[KT - 1] = row[kc_last];
@@ -821,7 +822,7 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
         else load1(ta, slab_of(i), 0);
     }
     for (; i < N; i += nw) {
-        const T *slab = slab_of(i);
+        const GF2_GLOBAL T *slab = slab_of(i);
         acc_t acc1[KT], acc1b[PT == 2 ? KT : 1];   // p tiles pt, pt + 1
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) acc1[kt] = acc_t{0, 0, 0, 0};
@@ -887,8 +888,8 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
         }
 
         // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p], one 16-row l tile at a time
-        T *xbase = X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
-        auto store = [&](T *xb, const acc_t &v, int lt) {
+        GF2_GLOBAL T *xbase = X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+        auto store = [&](GF2_GLOBAL T *xb, const acc_t &v, int lt) {
             if constexpr (MODE == MODE_F64) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -898,7 +899,7 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
             } else {
                 const int l0 = 16 * lt + 4 * g;
                 if (vec4 && l0 < N) {
-                    *reinterpret_cast<float4 *>(xb + l0) = make_float4(v[0], v[1], v[2], v[3]);
+                    *(GF2_GLOBAL v4f *)(xb + l0) = v4f{v[0], v[1], v[2], v[3]};
                 } else if (!vec4) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
@@ -1023,8 +1024,8 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
     const long long k0 = (long long)z * a.kz;
     const long long kend = std::min<long long>(a.K, k0 + a.kz);
     const int r0 = rb * BMR;
-    const T *X = static_cast<const T *>(a.X);
-    const T *W = static_cast<const T *>(a.W);
+    const GF2_GLOBAL T *X = (const GF2_GLOBAL T *)a.X;
+    const GF2_GLOBAL T *W = (const GF2_GLOBAL T *)a.W;
     const size_t RN = (size_t)a.R * N;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1051,7 +1052,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
             vec_t v;
             if (a.vec) {
                 if (k < kend && r < a.R) {
-                    v = *reinterpret_cast<const vec_t *>(X + (size_t)np * RN + (size_t)r * N + l);
+                    v = *(const GF2_GLOBAL vec_t *)(X + (size_t)np * RN + (size_t)r * N + l);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) v[e] = T(0);
@@ -1086,9 +1087,9 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
                 // reach outputs j >= N, and both read finite W2 values.
                 const long long gkc = gk < a.K ? gk : a.K - 1;
                 const int gcc = gc < N ? gc : N - VEC;
-                v = *reinterpret_cast<const vec_t *>(W + (size_t)gkc * N + gcc);
+                v = *(const GF2_GLOBAL vec_t *)(W + (size_t)gkc * N + gcc);
             } else {
-                const T *src = W + (size_t)gk * N + gc;
+                const GF2_GLOBAL T *src = W + (size_t)gk * N + gc;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[e] = (ok && gc + e < N) ? src[e] : T(0);
             }
@@ -1138,7 +1139,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
         }
     }
 
-    double *out = a.part + (size_t)z * RN;
+    GF2_GLOBAL double *out = (GF2_GLOBAL double *)a.part + (size_t)z * RN;
 #pragma unroll
     for (int cc = 0; cc < NT; ++cc)
 #pragma unroll
@@ -1324,12 +1325,12 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     // rows k >= N read row N - 1 (finite; they meet zero rows of G); q
     // blocks past the padded row read q = 0 (they meet zero rows of G(-tau))
     const int kc_last = min(16 * (KT - 1) + c, N - 1);
-    const unsigned short *T1p[NP];
+    const GF2_GLOBAL unsigned short *T1p[NP];
     const unsigned short *GSp[NP];
     const unsigned short *BSp[NP];
 #pragma unroll
     for (int pl = 0; pl < NP; ++pl) {
-        T1p[pl] = a.T1 + pl * a.t1_plane;
+        T1p[pl] = (const GF2_GLOBAL unsigned short *)a.T1 + pl * a.t1_plane;
         GSp[pl] = GS + pl * P16 * SLG;
         BSp[pl] = BS + pl * 16 * SQ + c * SQ + 8 * g;
     }
@@ -1350,7 +1351,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
                 const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
                 const size_t o = soff + (size_t)k * a.lq + q0;
 #pragma unroll
-                for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *reinterpret_cast<const v8us *>(T1p[pl] + o);
+                for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *(const GF2_GLOBAL v8us *)(T1p[pl] + o);
             }
         };
         load(0);
@@ -1380,7 +1381,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
                         const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
                         const size_t o = soff + (size_t)k * a.lq + q1;
 #pragma unroll
-                        for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *reinterpret_cast<const v8us *>(T1p[pl] + o);
+                        for (int pl = 0; pl < NP; ++pl) av[kt][pl] = *(const GF2_GLOBAL v8us *)(T1p[pl] + o);
                     }
                 }
             }
@@ -1398,7 +1399,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
             }
             split8<NP>(y, yv[u]);
         }
-        float *xbase = a.X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+        GF2_GLOBAL float *xbase = (GF2_GLOBAL float *)a.X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
 #pragma unroll 1
         for (int lt = 0; lt < KT; ++lt) {
             v4f acc2 = v4f{0, 0, 0, 0};
@@ -1413,7 +1414,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
             if (p < N) {
                 const int l0 = 16 * lt + 4 * g;
                 if (vec4 && l0 < N) {
-                    *reinterpret_cast<float4 *>(xbase + l0) = make_float4(acc2[0], acc2[1], acc2[2], acc2[3]);
+                    *(GF2_GLOBAL v4f *)(xbase + l0) = v4f{acc2[0], acc2[1], acc2[2], acc2[3]};
                 } else if (!vec4) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
@@ -1505,7 +1506,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             if (a.vec) {
                 const unsigned np = udiv22((unsigned)k, (unsigned)N, inv_n);
                 const int l = (int)(k - (long long)np * N);
-                ra[h] = *reinterpret_cast<const v4f *>(a.X + (size_t)np * RN + (size_t)r * N + l);
+                ra[h] = *(const GF2_GLOBAL v4f *)((const GF2_GLOBAL float *)a.X + (size_t)np * RN + (size_t)r * N + l);
             } else {
                 float x[4];
 #pragma unroll
@@ -1514,7 +1515,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
                     if (ke >= a.K) ke = 0;
                     const unsigned np = udiv22((unsigned)ke, (unsigned)N, inv_n);
                     const int l = (int)(ke - (long long)np * N);
-                    x[e] = a.X[(size_t)np * RN + (size_t)r * N + l];
+                    x[e] = ((const GF2_GLOBAL float *)a.X)[(size_t)np * RN + (size_t)r * N + l];
                 }
                 ra[h] = v4f{x[0], x[1], x[2], x[3]};
             }
@@ -1530,7 +1531,8 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             const int u = min(tid + j * S4_THREADS, B16 - 1);
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl)
-                rbv[j][pl] = *reinterpret_cast<const v8us *>(a.W2b + pl * a.plane + base + (size_t)u * 8);
+                rbv[j][pl] = *(const GF2_GLOBAL v8us *)((const GF2_GLOBAL unsigned short *)a.W2b + pl * a.plane +
+                                                        base + (size_t)u * 8);
         }
     };
     auto store_b = [&]() {
@@ -1583,7 +1585,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
         }
     }
 
-    double *out = a.part + (size_t)z * RN;
+    GF2_GLOBAL double *out = (GF2_GLOBAL double *)a.part + (size_t)z * RN;
 #pragma unroll
     for (int cc = 0; cc < NT; ++cc)
 #pragma unroll
