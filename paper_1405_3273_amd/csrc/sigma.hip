@@ -1274,24 +1274,37 @@ struct S23b3Args {
     int n, nb;
 };
 
+// p tiles per wave of the split S23 kernel: two for KT <= 7 (the T1 operands
+// of the first product and the G(tau) operands of the second are loaded once
+// for both tiles), one above (registers).  Each tile's products and their
+// order do not depend on this.
+template <int KT> struct S23bPt { static constexpr int value = (KT >= 2 && KT <= 7) ? 2 : 1; };
+static int s23b_pt(int kt) { return (kt >= 2 && kt <= 7) ? 2 : 1; }
+// workgroups per (tau, n)
+static int s23b_groups(int kt) { return (kt + s23b_pt(kt) - 1) / s23b_pt(kt); }
+
 template <int KT, int NP>
 __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     constexpr int KP = (KT + 1) / 2;          // 32-deep k steps of the second product
     constexpr int P16 = 16 * KT;
     constexpr int SLG = 32 * KP + 8;          // LDS row of Gq (bf16)
+    constexpr int PT = S23bPt<KT>::value;
+    constexpr int GR = (KT + PT - 1) / PT;    // workgroups per (t, nn)
     extern __shared__ __attribute__((aligned(16))) unsigned char s23b_smem[];
 
     S23b3Args a;
     int L;
-    if (!kresolve(ref, ref.one.nb * ref.one.n * KT, a, L)) return;
+    if (!kresolve(ref, ref.one.nb * ref.one.n * GR, a, L)) return;
     const int N = a.n;
-    const int pt = L % KT;
-    const int nn = (L / KT) % N;
-    const int t = L / (KT * N);
+    const int pt = (L % GR) * PT;             // first p tile of the workgroup
+    const int nn = (L / GR) % N;
+    const int t = L / (GR * N);
+    const bool two = PT == 2 && pt + 1 < KT;  // workgroup-uniform
     const int S32 = (N + 31) >> 5;            // 32-deep q steps of the first product
     const int SQ = 32 * S32 + 8;              // LDS row of the G(-tau) slice (bf16)
 
-    // NP planes of the Gq slice, then NP planes of [16][SQ]: G(-tau)[q][16 pt + c] at [c][q]
+    // NP planes of the Gq slice, then NP planes of [16 PT][SQ]:
+    // G(-tau)[q][16 pt + cc] at [cc][q]
     unsigned short *GS = reinterpret_cast<unsigned short *>(s23b_smem);
     unsigned short *BS = GS + NP * P16 * SLG;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -1305,13 +1318,13 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
             for (int e = tid; e < n16; e += nth) dst[e] = src[e];
         }
         const float *Gb = a.Gb + (size_t)t * N * N;
-        for (int e = tid; e < 16 * SQ; e += nth) {
+        for (int e = tid; e < 16 * PT * SQ; e += nth) {
             const int cc = e / SQ, q = e - cc * SQ, p = 16 * pt + cc;
             const float x = (q < N && p < N) ? Gb[(size_t)q * N + p] : 0.0f;
             unsigned short o[NP];
             split_bf16n<NP>(x, o);
 #pragma unroll
-            for (int pl = 0; pl < NP; ++pl) BS[pl * 16 * SQ + e] = o[pl];
+            for (int pl = 0; pl < NP; ++pl) BS[pl * 16 * PT * SQ + e] = o[pl];
         }
     }
     __syncthreads();
@@ -1332,14 +1345,16 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     for (int pl = 0; pl < NP; ++pl) {
         T1p[pl] = (const GF2_GLOBAL unsigned short *)a.T1 + pl * a.t1_plane;
         GSp[pl] = GS + pl * P16 * SLG;
-        BSp[pl] = BS + pl * 16 * SQ + c * SQ + 8 * g;
+        BSp[pl] = BS + pl * 16 * PT * SQ + c * SQ + 8 * g;
     }
 
     for (int i = tid >> 6; i < N; i += nw) {
         const size_t soff = (((size_t)i * a.nb + t) * N + nn) * slab_sz;
-        v4f acc1[2 * KP];
+        v4f acc1[2 * KP], acc1b[PT == 2 ? 2 * KP : 1];   // p tiles pt, pt + 1
 #pragma unroll
         for (int kt = 0; kt < 2 * KP; ++kt) acc1[kt] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int kt = 0; kt < (PT == 2 ? 2 * KP : 1); ++kt) acc1b[kt] = v4f{0, 0, 0, 0};
 
         // ---- Y^T[k][p] = sum_q T1[k][q] Gb[q][p]  (slab symmetric)
         v8us av[KT][NP];
@@ -1356,10 +1371,13 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
         };
         load(0);
         for (int s = 0; s < S32; ++s) {
-            v8us bv[NP];
+            v8us bv[NP], bw[NP];
 #pragma unroll
-            for (int pl = 0; pl < NP; ++pl) bv[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 32 * s);
-            if constexpr (NP == 2) {
+            for (int pl = 0; pl < NP; ++pl) {
+                bv[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 32 * s);
+                if constexpr (PT == 2) bw[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 16 * SQ + 32 * s);
+            }
+            if constexpr (NP == 2 && PT == 1 && KT < 10) {
                 // whole next step prefetched into a second register set
                 v8us cv[KT][NP];
 #pragma unroll
@@ -1370,13 +1388,15 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt) acc1[kt] = mma3<NP>(cv[kt], bv, acc1[kt]);
             } else {
-                // three planes: no room for a second set; each k tile's next
-                // operands are loaded into its registers once its products issue
+                // no room for a second set: each k tile's next operands are
+                // loaded into its registers once its products issue
                 int q1 = 32 * (s + 1) + 8 * g;
                 if (q1 + 8 > a.lq) q1 = 0;
 #pragma unroll
                 for (int kt = 0; kt < KT; ++kt) {
                     acc1[kt] = mma3<NP>(av[kt], bv, acc1[kt]);
+                    if constexpr (PT == 2)
+                        if (two) acc1b[kt] = mma3<NP>(av[kt], bw, acc1b[kt]);
                     if (s + 1 < S32) {
                         const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
                         const size_t o = soff + (size_t)k * a.lq + q1;
@@ -1388,7 +1408,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
         }
 
         // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p]; B operand = two result tiles
-        v8us yv[KP][NP];
+        v8us yv[KP][NP], yw[PT == 2 ? KP : 1][NP];
 #pragma unroll
         for (int u = 0; u < KP; ++u) {
             float y[8];
@@ -1398,11 +1418,29 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
                 y[4 + e] = acc1[2 * u + 1][e];
             }
             split8<NP>(y, yv[u]);
+            if constexpr (PT == 2) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    y[e] = acc1b[2 * u][e];
+                    y[4 + e] = acc1b[2 * u + 1][e];
+                }
+                split8<NP>(y, yw[u]);
+            }
         }
         GF2_GLOBAL float *xbase = (GF2_GLOBAL float *)a.X + ((size_t)(nn * N + p) * R + (size_t)t * N + i) * N;
+        auto store = [&](GF2_GLOBAL float *xb, const v4f &v, int lt) {
+            const int l0 = 16 * lt + 4 * g;
+            if (vec4 && l0 < N) {
+                *(GF2_GLOBAL v4f *)(xb + l0) = v4f{v[0], v[1], v[2], v[3]};
+            } else if (!vec4) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (l0 + e < N) xb[l0 + e] = v[e];
+            }
+        };
 #pragma unroll 1
         for (int lt = 0; lt < KT; ++lt) {
-            v4f acc2 = v4f{0, 0, 0, 0};
+            v4f acc2 = v4f{0, 0, 0, 0}, acc3 = v4f{0, 0, 0, 0};
             const int row = (16 * lt + c) * SLG + 8 * g;
 #pragma unroll
             for (int u = 0; u < KP; ++u) {
@@ -1410,17 +1448,11 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
 #pragma unroll
                 for (int pl = 0; pl < NP; ++pl) gv[pl] = *reinterpret_cast<const v8us *>(GSp[pl] + row + 32 * u);
                 acc2 = mma3<NP>(gv, yv[u], acc2);
+                if constexpr (PT == 2)
+                    if (two) acc3 = mma3<NP>(gv, yw[u], acc3);
             }
-            if (p < N) {
-                const int l0 = 16 * lt + 4 * g;
-                if (vec4 && l0 < N) {
-                    *(GF2_GLOBAL v4f *)(xbase + l0) = v4f{acc2[0], acc2[1], acc2[2], acc2[3]};
-                } else if (!vec4) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (l0 + e < N) xbase[l0 + e] = acc2[e];
-                }
-            }
+            if (p < N) store(xbase, acc2, lt);
+            if (two && p + 16 < N) store(xbase + (size_t)16 * R * N, acc3, lt);
         }
     }
 }
@@ -1699,7 +1731,7 @@ static size_t s23b3_lds(int n, int np) {
     constexpr int P16 = 16 * KT;
     constexpr int SLG = 32 * KP + 8;
     const int SQ = 32 * ((n + 31) / 32) + 8;
-    return 2 * (size_t)np * ((size_t)P16 * SLG + (size_t)16 * SQ);
+    return 2 * (size_t)np * ((size_t)P16 * SLG + (size_t)16 * S23bPt<KT>::value * SQ);
 }
 
 template <int KT, int NP>
@@ -2026,7 +2058,7 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
     }
     {
         const int np = split_planes(p.mode);
-        const int groups = np ? p.KT : s23_groups(p.mode, p.KT);
+        const int groups = np ? s23b_groups(p.KT) : s23_groups(p.mode, p.KT);
         const dim3 grid(xcd_grid((long long)nb * p.n * groups));
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_S23) : -1;
         if (np) {
@@ -2264,7 +2296,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                 std::vector<S23b3Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s23b3(plans[s], nb_of(s)));
-                    boff.push_back(boff.back() + nb_of(s) * plans[s].n * plans[s].KT);
+                    boff.push_back(boff.back() + nb_of(s) * plans[s].n * s23b_groups(plans[s].KT));
                     lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n, np));
                 }
                 push_table(buf, tab, boff, gl);
