@@ -140,11 +140,11 @@ def test_workload_size_transforms_sampled(torch):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_loop_on_power_grid_matches_oracle(torch, prec):
     """HF reference plus two correlated iterations of the N=10 workload on a
     129-point power grid: energies against the oracle's loop on the same grid
-    (FP64 to 1e-10 relative, FP32 Sigma to 1e-6 Eh)."""
+    (FP64 to 1e-10 relative, FP32 and BF16x6 Sigma to 1e-6 Eh)."""
     from paper_1405_3273_amd import make_params
     s = small_molecule()
     s.ntau = 129
