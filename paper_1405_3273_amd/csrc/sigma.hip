@@ -32,6 +32,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace gf2 {
@@ -989,6 +990,27 @@ struct S4Args {
     int ncb;            // column blocks of 16 * NT columns per row block (1 or 2)
 };
 
+// The final contraction orders its rows i-major: row r = i nb + t is X row
+// t n + i.  First 16-column tile (columns col0 + 16 cc) that a workgroup
+// needs: its smallest i is r0 / nb, and the reduction reads only the entries
+// j >= i, so tiles wholly below that i are skipped.  Workgroup-uniform.
+__device__ __forceinline__ int s4_first_tile(int r0, int nb, int col0) {
+    return max(0, (r0 / nb - col0) >> 4);
+}
+#define GF2_FIRST_TILE_SWITCH(first, run)                                                   \
+    switch (first) {                                                                        \
+        case 0: run(std::integral_constant<int, 0>{}); break;                               \
+        case 1: run(std::integral_constant<int, 1>{}); break;                               \
+        case 2: run(std::integral_constant<int, 2>{}); break;                               \
+        case 3: run(std::integral_constant<int, 3>{}); break;                               \
+        case 4: run(std::integral_constant<int, 4>{}); break;                               \
+        case 5: run(std::integral_constant<int, 5>{}); break;                               \
+        case 6: run(std::integral_constant<int, 6>{}); break;                               \
+        case 7: run(std::integral_constant<int, 7>{}); break;                               \
+        case 8: run(std::integral_constant<int, 8>{}); break;                               \
+        default: run(std::integral_constant<int, 9>{}); break;                              \
+    }
+
 constexpr int S4_WAVES = 8;               // one 16-row tile per wave
 constexpr int S4_THREADS = 64 * S4_WAVES;
 constexpr int S4_BM = 16 * S4_WAVES;
@@ -1041,6 +1063,14 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
     }
 
     const float inv_n = 1.0f / (float)N;
+    // X row of each staged logical row (i-major r = i nb + t -> X row t n + i)
+    const int nbt = a.R / N;
+    int xrow[A_IT];
+#pragma unroll
+    for (int j = 0; j < A_IT; ++j) {
+        const int r = min(r0 + arow + AROWS * j, a.R - 1);
+        xrow[j] = (r % nbt) * N + r / nbt;
+    }
     vec_t ra[A_IT], rbv[B_IT];
     auto load_chunk = [&](long long kb) {
         const long long k = kb + VEC * kq;
@@ -1049,10 +1079,11 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
 #pragma unroll
         for (int j = 0; j < A_IT; ++j) {
             const int r = r0 + arow + AROWS * j;
+            const int rp = xrow[j];
             vec_t v;
             if (a.vec) {
                 if (k < kend && r < a.R) {
-                    v = *(const GF2_GLOBAL vec_t *)(X + (size_t)np * RN + (size_t)r * N + l);
+                    v = *(const GF2_GLOBAL vec_t *)(X + (size_t)np * RN + (size_t)rp * N + l);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) v[e] = T(0);
@@ -1065,7 +1096,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
                     if (ke < kend && r < a.R) {
                         const unsigned npe = udiv22((unsigned)ke, (unsigned)N, inv_n);
                         const int le = (int)(ke - (long long)npe * N);
-                        x = X[(size_t)npe * RN + (size_t)r * N + le];
+                        x = X[(size_t)npe * RN + (size_t)rp * N + le];
                     }
                     v[e] = x;
                 }
@@ -1108,36 +1139,42 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
     };
 
     const int nchunks = (int)((kend - k0 + BK - 1) / BK);
-    load_chunk(k0);
-    for (int ch = 0; ch < nchunks; ++ch) {
-        __syncthreads();
-        store_chunk();
-        __syncthreads();
-        if (ch + 1 < nchunks) load_chunk(k0 + (long long)(ch + 1) * BK);
+    const int first = s4_first_tile(r0, a.R / N, col0);
+    if (first >= NT) return;   // workgroup-uniform: every entry here has j < i
+    auto run = [&](auto cf) {
+        constexpr int CF = decltype(cf)::value < NT ? decltype(cf)::value : NT;
+        load_chunk(k0);
+        for (int ch = 0; ch < nchunks; ++ch) {
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+            if (ch + 1 < nchunks) load_chunk(k0 + (long long)(ch + 1) * BK);
 #pragma unroll
-        for (int s4 = 0; s4 < BK; s4 += 4) {
-            const int kr = s4 + (lane >> 4);
-            const T af = As[wave * 16 + (lane & 15)][kr];
+            for (int s4 = 0; s4 < BK; s4 += 4) {
+                const int kr = s4 + (lane >> 4);
+                const T af = As[wave * 16 + (lane & 15)][kr];
 #pragma unroll
-            for (int cc = 0; cc < NT; ++cc) {
-                const T bf = Bs[kr][cc * 16 + (lane & 15)];
-                if constexpr (F64)
-                    acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[cc], 0, 0, 0);
-                else
-                    acc[cc] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[cc], 0, 0, 0);
+                for (int cc = CF; cc < NT; ++cc) {
+                    const T bf = Bs[kr][cc * 16 + (lane & 15)];
+                    if constexpr (F64)
+                        acc[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[cc], 0, 0, 0);
+                    else
+                        acc[cc] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[cc], 0, 0, 0);
+                }
             }
-        }
-        if constexpr (!F64) {
-            if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
+            if constexpr (!F64) {
+                if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
 #pragma unroll
-                for (int cc = 0; cc < NT; ++cc) {
+                    for (int cc = CF; cc < NT; ++cc) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
-                    acc[cc] = acc_t{0, 0, 0, 0};
+                        for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
+                        acc[cc] = acc_t{0, 0, 0, 0};
+                    }
                 }
             }
         }
-    }
+    };
+    GF2_FIRST_TILE_SWITCH(first, run)
 
     GF2_GLOBAL double *out = (GF2_GLOBAL double *)a.part + (size_t)z * RN;
 #pragma unroll
@@ -1177,14 +1214,20 @@ __global__ void k_symmetrize(int n, int ntau, double *__restrict__ Sig) {
 }
 
 // Sigma[k0 + t][i][j] = sum_z part[z][t*n + i][j]   (part already carries the minus sign)
+// The partial sums hold row i nb + t for (tau_t, i) (the final contraction's
+// i-major row order) and only the entries j >= i: Sigma_ij = Sigma_ji (symmetric G and integrals), so
+// (i, j) with j < i is the computed (j, i).
 __global__ void k_reduce_split(int n, int nb, int nsplit, const double *__restrict__ part,
                                double *__restrict__ Sig, int k0) {
     const size_t n2 = (size_t)n * n;
     const size_t total = n2 * nb;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t t = idx / n2, e = idx % n2;
+        const int i = (int)(e / n), j = (int)(e % n);
+        const size_t src = ((size_t)min(i, j) * nb + t) * n + max(i, j);
         double s = 0.0;
-        for (int z = 0; z < nsplit; ++z) s += part[z * total + idx];
+        for (int z = 0; z < nsplit; ++z) s += part[z * total + src];
         Sig[(size_t)k0 * n2 + idx] = s;
     }
 }
@@ -1517,6 +1560,8 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
     const int g = lane >> 4, c = lane & 15;
     const size_t RN = (size_t)a.R * N;
     const int r = std::min(rb * S4_BM + wave * 16 + c, a.R - 1);
+    const int nbt = a.R / N;
+    const int xr = (r % nbt) * N + r / nbt;   // X row of the i-major row r = i nb + t
 
     v4f acc[NT];
     double accd[NT][4];
@@ -1538,7 +1583,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
             if (a.vec) {
                 const unsigned np = udiv22((unsigned)k, (unsigned)N, inv_n);
                 const int l = (int)(k - (long long)np * N);
-                ra[h] = *(const GF2_GLOBAL v4f *)((const GF2_GLOBAL float *)a.X + (size_t)np * RN + (size_t)r * N + l);
+                ra[h] = *(const GF2_GLOBAL v4f *)((const GF2_GLOBAL float *)a.X + (size_t)np * RN + (size_t)xr * N + l);
             } else {
                 float x[4];
 #pragma unroll
@@ -1547,7 +1592,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
                     if (ke >= a.K) ke = 0;
                     const unsigned np = udiv22((unsigned)ke, (unsigned)N, inv_n);
                     const int l = (int)(ke - (long long)np * N);
-                    x[e] = ((const GF2_GLOBAL float *)a.X)[(size_t)np * RN + (size_t)r * N + l];
+                    x[e] = ((const GF2_GLOBAL float *)a.X)[(size_t)np * RN + (size_t)xr * N + l];
                 }
                 ra[h] = v4f{x[0], x[1], x[2], x[3]};
             }
@@ -1579,43 +1624,49 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4_bf3(KRef<S4b3Args> ref) {
     };
 
     const int nchunks = (int)((kend - k0 + BK - 1) / BK);
-    load_a(k0);
-    load_b(k0);
-    for (int ch = 0; ch < nchunks; ++ch) {
-        __syncthreads();
-        store_b();
-        __syncthreads();
-        v4f cur[4];
+    const int first = s4_first_tile(rb * S4_BM, a.R / N, 0);
+    if (first >= NT) return;   // workgroup-uniform: every entry here has j < i
+    auto run = [&](auto cf) {
+        constexpr int CF = decltype(cf)::value < NT ? decltype(cf)::value : NT;
+        load_a(k0);
+        load_b(k0);
+        for (int ch = 0; ch < nchunks; ++ch) {
+            __syncthreads();
+            store_b();
+            __syncthreads();
+            v4f cur[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) cur[h] = ra[h];
-        if (ch + 1 < nchunks) {
-            load_a(k0 + (long long)(ch + 1) * BK);
-            load_b(k0 + (long long)(ch + 1) * BK);
-        }
+            for (int h = 0; h < 4; ++h) cur[h] = ra[h];
+            if (ch + 1 < nchunks) {
+                load_a(k0 + (long long)(ch + 1) * BK);
+                load_b(k0 + (long long)(ch + 1) * BK);
+            }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            float x[8] = {cur[2 * s][0], cur[2 * s][1], cur[2 * s][2], cur[2 * s][3],
-                          cur[2 * s + 1][0], cur[2 * s + 1][1], cur[2 * s + 1][2], cur[2 * s + 1][3]};
-            v8us xv[NP];
-            split8<NP>(x, xv);
+            for (int s = 0; s < 2; ++s) {
+                float x[8] = {cur[2 * s][0], cur[2 * s][1], cur[2 * s][2], cur[2 * s][3],
+                              cur[2 * s + 1][0], cur[2 * s + 1][1], cur[2 * s + 1][2], cur[2 * s + 1][3]};
+                v8us xv[NP];
+                split8<NP>(x, xv);
 #pragma unroll
-            for (int cc = 0; cc < NT; ++cc) {
-                v8us bv[NP];
+                for (int cc = CF; cc < NT; ++cc) {
+                    v8us bv[NP];
 #pragma unroll
-                for (int pl = 0; pl < NP; ++pl)
-                    bv[pl] = *reinterpret_cast<const v8us *>(&Bs[pl][16 * cc + c][32 * s + 8 * g]);
-                acc[cc] = mma3<NP>(xv, bv, acc[cc]);
+                    for (int pl = 0; pl < NP; ++pl)
+                        bv[pl] = *reinterpret_cast<const v8us *>(&Bs[pl][16 * cc + c][32 * s + 8 * g]);
+                    acc[cc] = mma3<NP>(xv, bv, acc[cc]);
+                }
+            }
+            if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
+#pragma unroll
+                for (int cc = CF; cc < NT; ++cc) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
+                    acc[cc] = v4f{0, 0, 0, 0};
+                }
             }
         }
-        if ((ch + 1) % FLUSH == 0 || ch + 1 == nchunks) {
-#pragma unroll
-            for (int cc = 0; cc < NT; ++cc) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) accd[cc][e] += (double)acc[cc][e];
-                acc[cc] = v4f{0, 0, 0, 0};
-            }
-        }
-    }
+    };
+    GF2_FIRST_TILE_SWITCH(first, run)
 
     GF2_GLOBAL double *out = (GF2_GLOBAL double *)a.part + (size_t)z * RN;
 #pragma unroll
