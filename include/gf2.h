@@ -151,9 +151,9 @@ int gf2_set_system(gf2_ctx *ctx, int n, const double *S, const double *h, const 
 
 /* gf2_sigma_tau: Eq. (Sigma) at every tau point, G(-tau) from
  * antiperiodicity.  G_tau: device [ntau][n][n] FP64 (symmetric).
- * Sigma_tau: device [ntau][n][n] FP64 output (may not alias G_tau), the
- * contraction as computed (symmetric up to the rounding of the chosen
- * arithmetic; gf2_iterate replaces each pair (i, j), (j, i) by its mean).
+ * Sigma_tau: device [ntau][n][n] FP64 output (may not alias G_tau), exactly
+ * symmetric: Sigma_ij = Sigma_ji for symmetric G and integrals, so the
+ * entries j >= i are computed and (i, j), j < i, is a copy of (j, i).
  * prec: GF2_PREC_*.  dims->n must equal the n of gf2_set_system;
  * nelec, niw are ignored.  Returns GF2_ENONFINITE if the result holds a
  * NaN or Inf.
@@ -254,10 +254,9 @@ int gf2_density_fock(gf2_ctx *ctx, const gf2_dims *dims, const gf2_params *prm,
 /* gf2_iterate: one outer iteration of the Supplementary Material's loop.
  * iteration 0 (st->iteration == 0): the reference, step 2 with Sigma = 0
  * from st->F (the core guess h) -- a finite-beta Hartree-Fock solution.
- * iteration >= 1: Sigma(tau) from st->G_tau (step 3), each pair (i, j),
- * (j, i) replaced by its mean (Sigma is symmetric for real orbitals; the
- * rounding of the reduced-precision forms would otherwise seed an
- * antisymmetric part that the loop amplifies), damped against
+ * iteration >= 1: Sigma(tau) from st->G_tau (step 3; exactly symmetric as
+ * gf2_sigma_tau returns it, so the rounding of the reduced-precision forms
+ * seeds no antisymmetric part that the loop would amplify), damped against
  * st->Sigma_tau from the second correlated iteration on, transformed to
  * Sigma(i w); then the inner loop: passes of gf2_density_fock with the
  * density mixed by damped Pulay/Anderson mixing of (P_in, P_out - P_in)

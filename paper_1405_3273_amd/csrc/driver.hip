@@ -650,9 +650,9 @@ static int iter_sigma_post(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, g
                            const double2 **Sig, const double **Sig1, double *t_four) {
     const size_t nt = (size_t)d->ntau * c->n * c->n;
     double *Snew = c->it_Sig_new.as<double>();
-    // Sigma_ij = Sigma_ji for real orbitals: keep the rounding of the reduced-
-    // precision forms out of the antisymmetric part (it would grow in the loop)
-    GF2_TRY(sigma_symmetrize(c, d->ntau, Snew));
+    // (Sigma(tau) is exactly symmetric: the contraction computes the entries
+    // j >= i and copies them to (j, i), so the reduced-precision forms seed no
+    // antisymmetric part that the loop would amplify)
     int bad = 0;
     GF2_TRY(any_nonfinite(c, nt, Snew, &bad));
     if (bad) return fail(GF2_ENONFINITE, "gf2_iterate: non-finite self-energy");

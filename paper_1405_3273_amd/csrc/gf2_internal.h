@@ -160,7 +160,6 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                       const std::vector<double *> &Sig);
 void sigma_release(gf2_ctx *c);
 // Sigma(tau) pairs (i, j), (j, i) replaced by their mean (the outer loop's step)
-int sigma_symmetrize(gf2_ctx *c, int ntau, double *Sig);
 
 int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2 *Sig_iw,
                    double *Sig1);

@@ -1193,25 +1193,6 @@ __global__ __launch_bounds__(S4_THREADS) void k_s4(KRef<S4Args> ref) {
         }
 }
 
-// Sigma_ij(tau) = Sigma_ji(tau) for real orbitals.  The outer loop replaces
-// each computed pair by its mean, so no antisymmetric part (rounding of the
-// reduced-precision forms) enters the self-consistent iteration; the Sigma
-// call itself returns the contraction as computed.  Threads over
-// tau x n x n; the thread of (i, j), i < j, writes the pair.
-__global__ void k_symmetrize(int n, int ntau, double *__restrict__ Sig) {
-    const size_t n2 = (size_t)n * n;
-    const size_t total = n2 * ntau;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t t = idx / n2, e = idx % n2;
-        const int i = (int)(e / n), j = (int)(e % n);
-        if (j <= i) continue;
-        double *S = Sig + t * n2;
-        const double m = 0.5 * (S[(size_t)i * n + j] + S[(size_t)j * n + i]);
-        S[(size_t)i * n + j] = m;
-        S[(size_t)j * n + i] = m;
-    }
-}
 
 // Sigma[k0 + t][i][j] = sum_z part[z][t*n + i][j]   (part already carries the minus sign)
 // The partial sums hold row i nb + t for (tau_t, i) (the final contraction's
@@ -2479,16 +2460,6 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
     lead->sig_graph = exec;
     lead->sig_key = key;
     GF2_HIP(hipGraphLaunch(exec, lead->stream));
-    return GF2_OK;
-}
-
-int sigma_symmetrize(gf2_ctx *c, int ntau, double *Sig) {
-    const int n = c->n;
-    if (n < 2) return GF2_OK;
-    const size_t tot = (size_t)ntau * n * n;
-    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, c->stream, n, ntau, Sig);
-    GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
 

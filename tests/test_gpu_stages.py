@@ -49,6 +49,7 @@ def test_sigma_tau_matches_oracle(torch, n, ntau, prec):
     err = _relerr(got, ref)
     print(f"  rel err {err:.3e}")
     assert err <= TOL_SIGMA[prec]
+    assert np.array_equal(got, got.transpose(0, 2, 1))    # exactly symmetric
     g.close()
 
 
