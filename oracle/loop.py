@@ -42,6 +42,14 @@ Readings for what the paper leaves open (tolerances and order):
   second correlated iteration on;
 * outer convergence: |dE| < tol_E and max|dP| < tol_P between outer
   iterations.
+
+Pinned (tests/test_oracle_physics.py): iteration by iteration, the Sigma(tau)
+an iteration uses is the six-index sum of Eq. (Sigma) over the G(tau) the
+previous iteration handed on (the closed-form Hartree-Fock G(tau) after
+iteration 0), P = -2 G(beta-) of the handed-on G(tau), F = F(P), and E_2b
+equals the imaginary-time form of the two-body energy of the same pair; the
+converged state satisfies all of them at once, independently of the Sigma
+damping and the mixing depth.
 """
 from dataclasses import dataclass, field
 from typing import Optional

@@ -152,3 +152,99 @@ def test_n10_workload_converges_with_sigma_damping():
     assert conv
     assert reps[-1].e2b < 0.0
     assert np.trace(st.P @ s.S) == pytest.approx(s.nelec, abs=1e-8)
+
+
+# ---- composition of the outer loop (Supplementary Material, steps 2-3) ----------
+#
+# Each outer iteration must hand on the right objects: Sigma(tau) of Eq. (Sigma)
+# from the G(tau) the previous iteration produced, the inner loop at that fixed
+# Sigma, the Galitskii-Migdal energy from the Green's function / self-energy pair
+# of the last Dyson solve, and G(tau) from that same solve.  The checks below use
+# routes that do not go through the loop: the Hartree-Fock Green's function in
+# closed form (eigenvectors of the generalized problem), the literal six-index sum
+# of Eq. (Sigma), the imaginary-time form of the two-body energy,
+# E_2b = -int_0^beta tr[Sigma(tau) G(beta - tau)] dtau, and the density as
+# -2 G(beta-) of the handed-on G(tau).
+
+def _loop_case(ntau=1025):
+    return generic_system(4, 11, naux=8, beta=10.0, niw=1024, ntau=ntau)
+
+
+def _fock_direct(h, v, P):
+    """Eq. (FockMatrix) written out: F_ij = h_ij + sum_kl P_kl (v_ijlk - v_iklj / 2)."""
+    n = h.shape[0]
+    F = h.copy()
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                for l in range(n):
+                    F[i, j] += P[k, l] * (v[i, j, l, k] - 0.5 * v[i, k, l, j])
+    return F
+
+
+def test_loop_hands_on_sigma_and_green_function_iteration_by_iteration():
+    s = _loop_case()
+    p = O.Params(tol_P=1e-12, tol_N=1e-12, damp_Sigma=0.0)
+    st = O.State(mu=-1.0, F=s.h.copy())
+    O.outer_iteration(s, p, st)
+    # iteration 0 is the finite-beta Hartree-Fock solution: its G(tau) is the
+    # closed form at the final F and mu
+    tau = O.tau_grid(s.beta, s.ntau)
+    G_hf = R.hf_green_tau(s.S, st.F, st.mu, s.beta, tau)
+    assert np.max(np.abs(st.G_tau - G_hf)) < 1e-9
+    ks = [0, 1, 300, 512, 1023, 1024]
+    G_prev = G_hf
+    for it in (1, 2, 3):
+        rep = O.outer_iteration(s, p, st)
+        # Sigma(tau) of this iteration = Eq. (Sigma) (six-index sum) of the previous G(tau)
+        Gb = O.gbar_from_gtau(G_prev)
+        ref = np.stack([O.sigma_bruteforce(G_prev[k], Gb[k], s.v) for k in ks])
+        tol = 1e-9 if it == 1 else 1e-12      # iteration 1: closed form vs transformed G_HF
+        assert np.max(np.abs(st.Sigma_tau[ks] - ref)) < tol * np.max(np.abs(ref))
+        # the density and the handed-on G(tau) come from the same (last) Dyson solve
+        assert np.max(np.abs(st.P + 2.0 * st.G_tau[-1])) < 1e-12
+        assert np.trace(st.P @ s.S) == pytest.approx(s.nelec, abs=1e-10)
+        # F = F(P) and the one-body energy of that pair
+        assert np.max(np.abs(st.F - _fock_direct(s.h, s.v, st.P))) < 1e-12
+        assert rep.e1b == pytest.approx(0.5 * np.sum(st.P * (s.h + st.F)), abs=1e-12)
+        # E_2b of the Sigma used in the inner loop and the G of its last solve
+        # (imaginary-time form; Simpson on 1025 points is good to ~1e-8 Eh here)
+        assert rep.e2b == pytest.approx(e_two_body_tau(st.Sigma_tau, st.G_tau, s.beta), abs=1e-7)
+        assert rep.energy == pytest.approx(rep.e1b + rep.e2b, abs=1e-14)
+        G_prev = st.G_tau.copy()
+
+
+@pytest.mark.slow
+def test_converged_loop_is_a_fixed_point_of_the_equations():
+    """Run to |dE| < 1e-12: the final state satisfies Eq. (Sigma), Eq. (GF) with
+    the density as -2 G(beta-), Eq. (FockMatrix), tr(PS) = N_e and the energy
+    functional at once, and the fixed point does not depend on the Sigma damping
+    or on the depth of the density mixing."""
+    s = _loop_case(ntau=513)
+    energies, dens = [], []
+    # plain damping (mix_depth 1) needs a heavier density damping on this system
+    for damp, depth, damp_P in ((0.3, 8, 0.3), (0.5, 8, 0.3), (0.3, 1, 0.7), (0.5, 1, 0.7)):
+        p = O.Params(tol_P=1e-12, tol_N=1e-12, tol_E=1e-12, damp_Sigma=damp, mix_depth=depth,
+                     damp_P=damp_P, max_inner=1000, max_outer=300)
+        st, reps, conv = O.run(s, p, mu0=-1.0)
+        assert conv, (damp, depth)
+        energies.append(st.energy)
+        dens.append(st.P)
+        if (damp, depth) != (0.3, 8):
+            continue
+        # Eq. (Sigma): the stored (damped) Sigma(tau) is Sigma[G(tau)] of the final G
+        ks = [0, 5, 256, 400, 512]
+        Gb = O.gbar_from_gtau(st.G_tau)
+        ref = np.stack([O.sigma_bruteforce(st.G_tau[k], Gb[k], s.v) for k in ks])
+        assert np.max(np.abs(st.Sigma_tau[ks] - ref)) < 1e-10 * np.max(np.abs(ref))
+        # density = -2 G(beta-), particle number, Eq. (FockMatrix)
+        assert np.max(np.abs(st.P + 2.0 * st.G_tau[-1])) < 1e-12
+        assert np.trace(st.P @ s.S) == pytest.approx(s.nelec, abs=1e-10)
+        assert np.max(np.abs(st.F - _fock_direct(s.h, s.v, st.P))) < 1e-11
+        # energy functional of the final pair (imaginary-time E_2b, Simpson on 513 points)
+        e1 = 0.5 * np.sum(st.P * (s.h + st.F))
+        assert st.energy == pytest.approx(e1 + e_two_body_tau(st.Sigma_tau, st.G_tau, s.beta),
+                                          abs=1e-6)
+        assert reps[-1].e2b < 0.0
+    assert max(energies) - min(energies) < 1e-10
+    assert max(float(np.max(np.abs(d - dens[0]))) for d in dens) < 1e-9
