@@ -329,7 +329,7 @@ int gf2_ctx_destroy(gf2_ctx *c) {
                            &c->dys_out,  &c->fock_part, &c->occ_ws, &c->grid_tau, &c->grid_thom, &c->grid_W, &c->grid_T,
                            &c->grid_coef, &c->grid_plan, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
                            &c->it_mom,   &c->it_Sig_new, &c->it_Pout, &c->it_Pin,  &c->it_F,
-                           &c->it_tmp,   &c->it_hist,   &c->host_stage, &c->bat_tab,  &c->bat_boff,
+                           &c->it_tmp,   &c->it_hist,   &c->bat_tab,  &c->bat_boff,
                            &c->bat_out,  &c->sig_tab,  &c->it_red,  &c->bat_red};
     for (auto *b : bufs) b->release();
     if (c->bat_red_h) (void)hipHostFree(c->bat_red_h);

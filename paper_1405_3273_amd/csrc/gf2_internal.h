@@ -115,7 +115,6 @@ struct gf2_ctx {
     void *sig_graph = nullptr;            // hipGraphExec_t of the batched Sigma
     long long sig_key = 0;
     long long bat_key = 0;                // shape the graph was captured for
-    gf2::DevBuf host_stage;               // unused placeholder for pinned staging
 };
 
 namespace gf2 {
@@ -159,7 +158,6 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                       int prec, const std::vector<const double *> &G,
                       const std::vector<double *> &Sig);
 void sigma_release(gf2_ctx *c);
-// Sigma(tau) pairs (i, j), (j, i) replaced by their mean (the outer loop's step)
 
 int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2 *Sig_iw,
                    double *Sig1);

@@ -699,10 +699,6 @@ template <int MODE> struct S23Geom {
     static constexpr int pad = (MODE == MODE_F64) ? 2 : 4;   // conflict-free 16-B row reads
 };
 
-#ifndef S23_DB
-#define S23_DB 1      // double-buffered operand groups in the first product
-#endif
-
 // Workgroup size bound: the grouped FP32 form keeps 100-200 registers live
 // (at most 8 waves); the FP64 form fits in 128 registers up to 7 tiles and
 // then runs 16 waves per workgroup, which is what one workgroup per CU
@@ -797,10 +793,7 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
     const int elast = __builtin_amdgcn_readfirstlane((N - 16 * (KT - 1) + 3) >> 2);
     auto slab_of = [&](int i) { return T1 + (((size_t)i * a.nb + t) * N + nn) * N2; };
     typedef T qv_t __attribute__((ext_vector_type(GW)));
-    qv_t ga_[KT];                               // grouped operands (GW steps each)
-#if S23_DB
-    qv_t gb_[KT];
-#endif
+    qv_t ga_[KT], gb_[KT];                      // grouped operands (GW steps each), double-buffered
     T ta[KT];                                   // one step of the remaining q
     auto loadg = [&](qv_t(&r)[KT], const GF2_GLOBAL T *slab, int u) {
         const GF2_GLOBAL T *col = slab + 4 * GW * u + GW * g;
@@ -860,7 +853,6 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
         if (U > 0) {
             // the first ungrouped step is loaded now; it is used last
             if (GW * U < S) load1(ta, slab, GW * U);
-#if S23_DB
             int u = 0;
             for (; u + 1 < U; u += 2) {
                 loadg(gb_, slab, u + 1);
@@ -869,12 +861,6 @@ __global__ __launch_bounds__((S23Threads<MODE, KT>::value)) void k_s23(KRef<S23A
                 stepg(gb_, u + 1);
             }
             if (u < U) stepg(ga_, u);
-#else
-            for (int u = 0; u < U; ++u) {
-                stepg(ga_, u);
-                if (u + 1 < U) loadg(ga_, slab, u + 1);
-            }
-#endif
         }
         // remaining steps: the first was loaded ahead, later ones (N % 16 >= 8
         // or N % 4 != 0) are loaded just before use
