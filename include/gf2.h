@@ -214,6 +214,29 @@ int gf2_dyson(gf2_ctx *ctx, const gf2_dims *dims, int mode, double mu,
               const double *F, const void *Sigma_iw, const double *Sigma1,
               void *G_iw, double *P, double *host_out);
 
+/* gf2_dyson_noalloc: gf2_dyson for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, modes, results and errors as
+ * gf2_dyson (the same kernels on the same workgroups, so the same bits); the
+ * workspace (tail moments, per-workgroup partial sums, reduced results) is a
+ * fixed device array of GF2_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, instead of context memory, so
+ * the call makes no hipMalloc/hipFree or other allocating call.  The context
+ * itself (gf2_ctx_create, gf2_set_system) is set up beforehand as usual.
+ * All calls on one GPU share that array: calls that overlap on one GPU
+ * (other host threads, other contexts' streams) race and must be serialised
+ * by the caller.  Workspace: 48 n^2 bytes of moments plus 32 bytes per
+ * partial-sum slot (at most 8 per CU) and, for FULL/ENERGY, n^2 doubles per
+ * P partial (one per workgroup: 2 per CU for n > 48); a solve that needs more
+ * than GF2_NOALLOC_SCRATCH_BYTES returns GF2_EINVAL and changes nothing (on
+ * a 256-CU MI355X: TRACE for every n <= 160, FULL/ENERGY up to n = 127).
+ * Synchronises the context's stream (host_out).
+ */
+#define GF2_NOALLOC_SCRATCH_BYTES (64u << 20)
+int gf2_dyson_noalloc(gf2_ctx *ctx, const gf2_dims *dims, int mode, double mu,
+                      const double *F, const void *Sigma_iw, const double *Sigma1,
+                      void *G_iw, double *P, double *host_out);
+
 /* gf2_fock: Eq. (FockMatrix) F = h + J(P) - K(P)/2 for the system's h and
  * v.  P, F: device [n][n] (may not alias).
  */

@@ -42,7 +42,7 @@ GF2_MU_SECANT = 2
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
             "gf2_iterate", "gf2_iterate_batched", "gf2_natural_occupations", "gf2_set_tau_grid",
-            "gf2_profile_enable", "gf2_profile_read")
+            "gf2_profile_enable", "gf2_profile_read", "gf2_dyson_noalloc")
 
 GF2_KC_SIGMA_GEMM = 0
 GF2_KC_SIGMA_SPLITK = 1
@@ -113,6 +113,7 @@ def load(path: str = None):
         "gf2_sigma_tau": ([vp, C.POINTER(gf2_dims), i, vp, vp], i),
         "gf2_fourier": ([vp, C.POINTER(gf2_dims), i, vp, vp, vp, vp], i),
         "gf2_dyson": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
+        "gf2_dyson_noalloc": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
         "gf2_fock": ([vp, vp, vp], i),
         "gf2_natural_occupations": ([vp, vp, vp], i),
         "gf2_set_tau_grid": ([vp, i, vp], i),
@@ -202,6 +203,15 @@ def gf2_dyson(ctx, dims: gf2_dims, mode, mu, F, Sigma_iw=None, Sigma1=None, G_iw
     out = (C.c_double * 2)()
     _check(load().gf2_dyson(ctx, C.byref(dims), int(mode), float(mu), _ptr(F), _ptr(Sigma_iw),
                             _ptr(Sigma1), _ptr(G_iw), _ptr(P), out))
+    return out[0], out[1]
+
+
+def gf2_dyson_noalloc(ctx, dims: gf2_dims, mode, mu, F, Sigma_iw=None, Sigma1=None, G_iw=None,
+                      P=None):
+    """gf2_dyson on the library's fixed per-GPU workspace (allocates nothing)."""
+    out = (C.c_double * 2)()
+    _check(load().gf2_dyson_noalloc(ctx, C.byref(dims), int(mode), float(mu), _ptr(F),
+                                    _ptr(Sigma_iw), _ptr(Sigma1), _ptr(G_iw), _ptr(P), out))
     return out[0], out[1]
 
 

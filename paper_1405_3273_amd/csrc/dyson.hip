@@ -22,6 +22,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace gf2 {
@@ -887,21 +891,37 @@ static int dyson_post(const DysonJob &j, const double *h, double *out) {
     return GF2_OK;
 }
 
-int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
-              const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
-              double *mom_out, double *out, double *trace_n) {
+// Device workspace of one single-system solve: tail moments and their
+// scratch ([6][n][n]), per-slot (trace, energy, flag) partials, the reduced
+// results and, for FULL/ENERGY, the P partials.  Every kernel writes (or
+// zeroes) what it later reads, so the workspace needs no clearing.
+struct DysonWs {
+    double *X, *aux, *out, *part;
+};
+struct DysonWsSize {
+    int nblocks;
+    size_t x, aux, out, part;   // bytes
+};
+static DysonWsSize dyson_ws_size(gf2_ctx *c, int n, int niw, int mode) {
+    DysonWsSize s{};
+    const size_t ne = (size_t)n * n;
+    s.nblocks = dyson_slots(c, n, niw);
+    s.x = 6 * ne * 8;
+    s.aux = (size_t)s.nblocks * 4 * 8 + 64;
+    s.out = 8 * 8;
+    s.part = mode != GF2_DYSON_TRACE ? part_layout(n, s.nblocks, mode).bytes : 0;
+    return s;
+}
+
+static int dyson_run_ws(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
+                        const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
+                        double *mom_out, double *out, double *trace_n, int nblocks,
+                        const DysonWs &ws) {
     const int n = c->n, niw = d->niw;
     const size_t ne = (size_t)n * n;
-    if (n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
     const bool full = mode != GF2_DYSON_TRACE;
-    const int nblocks = dyson_slots(c, n, niw);
     const size_t shm = dyson_shm(n, mode);
-
-    GF2_TRY(c->dys_X.ensure(6 * ne * 8));
-    GF2_TRY(c->dys_aux.ensure((size_t)nblocks * 4 * 8 + 64));
-    GF2_TRY(c->dys_out.ensure(8 * 8));
     const PartLayout pl = part_layout(n, nblocks, mode);
-    if (full) GF2_TRY(c->dys_part.ensure(pl.bytes));
 
     DysonRef g{};
     DysonJob &a = g.one;
@@ -913,13 +933,13 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     a.Sig1 = full ? Sig1 : nullptr;
     a.Sig = Sig_iw; a.G = full ? G_iw : nullptr;
     a.P = full ? P : nullptr;
-    a.mom = c->dys_X.as<double>();
+    a.mom = ws.X;
     a.scr = a.mom + 3 * ne;
-    a.partP = full ? c->dys_part.as<double>() : nullptr;
-    a.partW = full ? c->dys_part.as<double>() + pl.off_w : nullptr;
+    a.partP = full ? ws.part : nullptr;
+    a.partW = full ? ws.part + pl.off_w : nullptr;
     a.npw = pl.npw;
-    a.parts = c->dys_aux.as<double>();
-    a.out = c->dys_out.as<double>();
+    a.parts = ws.aux;
+    a.out = ws.out;
     g.nsys = 0;
 
     launch_moments(g, 1, (int)ne, c->stream);
@@ -942,6 +962,49 @@ int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *
     if (trace_n) *trace_n = o[2];
     return GF2_OK;
 }
+
+int dyson_run(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
+              const double2 *Sig_iw, const double *Sig1, double2 *G_iw, double *P,
+              double *mom_out, double *out, double *trace_n) {
+    if (c->n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson: n > 160 is not supported");
+    const DysonWsSize s = dyson_ws_size(c, c->n, d->niw, mode);
+    GF2_TRY(c->dys_X.ensure(s.x));
+    GF2_TRY(c->dys_aux.ensure(s.aux));
+    GF2_TRY(c->dys_out.ensure(s.out));
+    if (s.part) GF2_TRY(c->dys_part.ensure(s.part));
+    const DysonWs ws{c->dys_X.as<double>(), c->dys_aux.as<double>(), c->dys_out.as<double>(),
+                     c->dys_part.as<double>()};
+    return dyson_run_ws(c, d, mode, mu, F, Sig_iw, Sig1, G_iw, P, mom_out, out, trace_n,
+                        s.nblocks, ws);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of gf2_dyson_noalloc: one fixed device array per GPU, allocated
+// with the code object, so the call itself allocates nothing.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name in host code is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[GF2_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_ptr;   // device -> address of its scratch
+
+static int scratch_address(int device, unsigned char **ptr) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *ptr = it->second;
+        return GF2_OK;
+    }
+    void *p = nullptr;
+    GF2_HIP(hipSetDevice(device));
+    GF2_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GF2_EHIP, "gf2_dyson_noalloc: no address for the scratch array");
+    *ptr = static_cast<unsigned char *>(p);
+    g_scratch_ptr[device] = *ptr;
+    return GF2_OK;
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
 // ---------------------------------------------------------------------------
 // Batched rounds.  The jobs of all systems sit in one device table ordered by
@@ -1156,17 +1219,50 @@ int dyson_round(gf2_ctx *lead, const std::vector<DysonReq> &req, std::vector<dou
 
 using namespace gf2;
 
+static int dyson_check(gf2_ctx *c, const gf2_dims *d, int mode, const double *F, double *P,
+                       double *host_out, const char *who) {
+    if (!c || !d || !F || !host_out) return fail(GF2_EINVAL, std::string(who) + ": NULL argument");
+    if (!c->has_system) return fail(GF2_ESTATE, std::string(who) + ": no system set");
+    if (d->n != c->n) return fail(GF2_EINVAL, std::string(who) + ": dims->n differs from the system");
+    if (d->niw < 1 || !(d->beta > 0.0)) return fail(GF2_EINVAL, std::string(who) + ": bad niw or beta");
+    if (mode < GF2_DYSON_TRACE || mode > GF2_DYSON_ENERGY)
+        return fail(GF2_EINVAL, std::string(who) + ": bad mode");
+    if (mode != GF2_DYSON_TRACE && !P) return fail(GF2_EINVAL, std::string(who) + ": FULL/ENERGY need P");
+    return GF2_OK;
+}
+
 extern "C" int gf2_dyson(gf2_ctx *c, const gf2_dims *d, int mode, double mu, const double *F,
                          const void *Sigma_iw, const double *Sigma1, void *G_iw, double *P,
                          double *host_out) {
-    if (!c || !d || !F || !host_out) return fail(GF2_EINVAL, "gf2_dyson: NULL argument");
-    if (!c->has_system) return fail(GF2_ESTATE, "gf2_dyson: no system set");
-    if (d->n != c->n) return fail(GF2_EINVAL, "gf2_dyson: dims->n differs from the system");
-    if (d->niw < 1 || !(d->beta > 0.0)) return fail(GF2_EINVAL, "gf2_dyson: bad niw or beta");
-    if (mode < GF2_DYSON_TRACE || mode > GF2_DYSON_ENERGY)
-        return fail(GF2_EINVAL, "gf2_dyson: bad mode");
-    if (mode != GF2_DYSON_TRACE && !P) return fail(GF2_EINVAL, "gf2_dyson: FULL/ENERGY need P");
+    GF2_TRY(dyson_check(c, d, mode, F, P, host_out, "gf2_dyson"));
     GF2_HIP(hipSetDevice(c->device));
     return dyson_run(c, d, mode, mu, F, static_cast<const double2 *>(Sigma_iw), Sigma1,
                      static_cast<double2 *>(G_iw), P, nullptr, host_out);
+}
+
+extern "C" int gf2_dyson_noalloc(gf2_ctx *c, const gf2_dims *d, int mode, double mu,
+                                 const double *F, const void *Sigma_iw, const double *Sigma1,
+                                 void *G_iw, double *P, double *host_out) {
+    GF2_TRY(dyson_check(c, d, mode, F, P, host_out, "gf2_dyson_noalloc"));
+    if (c->n > DY_MAXN) return fail(GF2_EINVAL, "gf2_dyson_noalloc: n > 160 is not supported");
+    unsigned char *base = nullptr;
+    GF2_TRY(scratch_address(c->device, &base));
+    GF2_HIP(hipSetDevice(c->device));
+    const DysonWsSize s = dyson_ws_size(c, c->n, d->niw, mode);
+    const size_t need = round256(s.x) + round256(s.aux) + round256(s.out) + round256(s.part);
+    if (need > (size_t)GF2_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        std::snprintf(buf, sizeof(buf),
+                      "gf2_dyson_noalloc: this solve needs %zu bytes of workspace, more than the "
+                      "fixed %zu (use gf2_dyson)", need, (size_t)GF2_NOALLOC_SCRATCH_BYTES);
+        return fail(GF2_EINVAL, buf);
+    }
+    DysonWs ws{};
+    size_t off = 0;
+    ws.X = reinterpret_cast<double *>(base + off);   off += round256(s.x);
+    ws.aux = reinterpret_cast<double *>(base + off); off += round256(s.aux);
+    ws.out = reinterpret_cast<double *>(base + off); off += round256(s.out);
+    ws.part = s.part ? reinterpret_cast<double *>(base + off) : nullptr;
+    return dyson_run_ws(c, d, mode, mu, F, static_cast<const double2 *>(Sigma_iw), Sigma1,
+                        static_cast<double2 *>(G_iw), P, nullptr, host_out, nullptr, s.nblocks, ws);
 }
