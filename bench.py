@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 METRIC = "GF2 iterations/s + Σ(τ) TFLOP/s at N=100,nτ=512; FP32/BF16-split vs FP64"
 
 PEAK = {  # MI355X published dense peaks
-    "fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "bf16x6": 2.5e15, "hbm": 8.0e12, "fp64_vector": 78.6e12,
+    "fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "bf16x6": 2.5e15, "bf16mix": 2.5e15, "hbm": 8.0e12, "fp64_vector": 78.6e12,
 }
 
 WORKLOADS = {
@@ -37,6 +37,8 @@ WORKLOADS = {
             "ntau=257, seed 0"),
     "n160": ("molecule_n160", "generic-n160: N=160, 160 electrons, half-band 16, naux=640, "
              "beta=200, niw=16384, ntau=512, seed 400"),
+    "c2": ("batched_member", "batched-sweep-64: 64 generic systems, even N drawn from [8, 48] "
+           "(seed 199), N electrons, naux=3N, beta=100, niw=4096, ntau=513, seeds 200..263"),
 }
 
 
@@ -119,21 +121,134 @@ def cpu_baseline(sysm, counts, sample_tau=3, sample_freq=512):
     }
 
 
+def cpu_baseline_sweep(members, solves_per_system, sample_freq=64):
+    """The oracle on a bounded sample of one batched outer iteration: Eq. (Sigma)
+    at one tau point of every member and Eq. (GF) at `sample_freq` frequencies of
+    every member, scaled to all tau points, all frequencies and the GPU
+    iteration's Dyson solves per system."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t_sig = t_dys = 0.0
+    for m in members:
+        rng = np.random.default_rng(0)
+        Gt = 0.05 * rng.standard_normal((m.ntau, m.n, m.n))
+        Gt = 0.5 * (Gt + Gt.transpose(0, 2, 1))
+        t0 = time.perf_counter()
+        O.sigma_tau(Gt, m.v, taus=[1])
+        t_sig += (time.perf_counter() - t0) * m.ntau
+        ns = np.arange(sample_freq) * (m.niw // sample_freq)
+        t0 = time.perf_counter()
+        G = O.green_iw(-1.0, m.S, m.h, None, m.beta, m.niw, n_idx=ns)
+        _ = float(np.einsum("nij,ji->", G.real, m.S))
+        t_dys += (time.perf_counter() - t0) / sample_freq * m.niw * solves_per_system
+    t_iter = t_sig + t_dys
+    return {"value": 1.0 / t_iter, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"Eq. (Sigma) at 1 tau point of each of the {len(members)} systems "
+                       f"({t_sig:.1f} s scaled to every tau point) and Eq. (GF) at {sample_freq} "
+                       f"frequencies of each ({t_dys:.1f} s scaled to all frequencies x "
+                       f"{solves_per_system:.1f} solves per system)"),
+            "seconds_per_iteration": t_iter}
+
+
+def run_sweep(args, desc):
+    """The batched sweep: one step is one outer iteration of all 64 systems
+    through gf2_iterate_batched (Sigma(tau) of every system in one captured
+    graph, the inner loops in lockstep, one captured graph per Dyson round)."""
+    import numpy as np
+    import torch
+    import synthetic
+    from paper_1405_3273_amd import _lib as L
+    from paper_1405_3273_amd.runtime import Gf2, Gf2Batch
+
+    t0 = time.perf_counter()
+    members = [synthetic.batched_member(k) for k in range(64)]
+    log(f"workload {desc} generated in {time.perf_counter() - t0:.1f} s")
+    batch = Gf2Batch([Gf2(m.S, m.h, m.v, nelec=m.nelec, beta=m.beta, niw=m.niw, ntau=m.ntau)
+                      for m in members])
+    batch.reset()
+    # 12 mixing pairs, damping 0.5: with the default 8 and 0.3 one member (n = 22,
+    # Hartree-Fock gap 0.01 Eh at beta = 100) stalls near max|dP| = 1e-6
+    prm = L.make_params(prec=args.prec, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel, damp_P=0.5,
+                        mix_depth=12, max_inner=200)
+    for w in range(args.warmup):
+        reps = batch.iterate(prm)
+        log(f"warmup {w}: {reps[0].ms_total:.0f} ms (sigma {reps[0].ms_sigma:.0f}, "
+            f"inner {reps[0].ms_inner:.0f}); max inner passes {max(r.n_inner for r in reps)}")
+    lead = batch.systems[0].ctx
+    torch.cuda.synchronize()
+    L.gf2_profile_enable(lead, True)
+    steps = args.steps
+    all_reps = []
+    t_start = time.perf_counter()
+    for k in range(steps):
+        reps = batch.iterate(prm)
+        all_reps.append(reps)
+        log(f"step {k}: {reps[0].ms_total:.0f} ms (sigma {reps[0].ms_sigma:.0f}, fourier "
+            f"{reps[0].ms_fourier:.0f}, inner {reps[0].ms_inner:.0f}); max |dE| "
+            f"{max(abs(r.dE) for r in reps):.2e}; max inner passes {max(r.n_inner for r in reps)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = L.gf2_profile_read(lead)
+    L.gf2_profile_enable(lead, False)
+    sig_flops = sum(sigma_flops(m.n, m.ntau) for m in members)
+    ms_sigma = float(np.mean([r[0].ms_sigma for r in all_reps]))
+    achieved = sig_flops / (ms_sigma / 1e3)
+    pk = PEAK[args.prec]
+    dy_ms, dy_n, dy_work = prof["dyson"]
+    line = {
+        "metric": METRIC, "value": steps / elapsed, "unit": "iterations/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16",
+                  "bf16mix": "bf16+f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": desc, "systems": len(members),
+                   "sizes": [int(m.n) for m in members], "sigma_arithmetic": args.prec,
+                   "other_stages": "f64", "damp_Sigma": prm.damp_Sigma,
+                   "mu_tol_N_rel": prm.tol_N_rel, "mix_depth": prm.mix_depth,
+                   "damp_P": prm.damp_P,
+                   "step": "one outer iteration of all systems"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": pk / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
+                     "kernel": "sigma_graph (all Sigma(tau) launches of the 64 systems, one "
+                               "captured graph; host clock around the synchronised replay)",
+                     "launches": steps, "avg_launch_ms": ms_sigma, "work_per_launch": sig_flops},
+        "dyson_rounds": {"launches": dy_n, "ms": dy_ms,
+                         "tflops": (dy_work / (dy_ms / 1e3) / 1e12) if dy_ms > 0 else None},
+        "per_step": {"ms_sigma": ms_sigma,
+                     "ms_fourier": float(np.mean([r[0].ms_fourier for r in all_reps])),
+                     "ms_inner": float(np.mean([r[0].ms_inner for r in all_reps])),
+                     "max_inner_passes": float(np.mean([max(x.n_inner for x in r) for r in all_reps])),
+                     "energies": [r.energy for r in all_reps[-1]]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        solves = dy_n / steps     # Dyson rounds per step: each round solves every pending system
+        line["cpu_baseline"] = cpu_baseline_sweep(members, solves)
+    batch.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
     ap.add_argument("--workload", default="n100", choices=sorted(WORKLOADS))
-    ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3,bf16x6",
+    ap.add_argument("--sigma-prec", default="fp64,fp32,bf16x3,bf16x6,bf16mix",
                     help="precisions for the stand-alone Sigma(tau) timing ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mu-tol-rel", type=float, default=1e-2,
                     help="inexact mu search in early inner passes: tolerance\n"
                          "max(tol_N, rel * max|dP| of the previous pass); each inner loop still\n"
                          "ends on a pass that used tol_N (0 = tol_N throughout)")
-    ap.add_argument("--forms", default="fp64,bf16x3,bf16x6",
+    ap.add_argument("--forms", default="fp64,bf16x3,bf16x6,bf16mix",
                     help="other Sigma precisions run through the same iterations from the same\n"
                          "start, for the whole-iteration speedup and energy difference against\n"
                          "the FP64 form ('' to skip)")
@@ -161,6 +276,8 @@ def main():
         del a, b
 
     gen, desc = WORKLOADS[args.workload]
+    if args.workload == "c2":
+        return run_sweep(args, desc)
     t0 = time.perf_counter()
     sysm = getattr(synthetic, gen)()
     log(f"workload {desc} generated in {time.perf_counter() - t0:.1f} s")
@@ -282,7 +399,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "bf16mix": "bf16+f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": desc, "sigma_arithmetic": args.prec,
                    "other_stages": "f64", "inner_tol_P": prm.tol_P, "damp_Sigma": prm.damp_Sigma,

@@ -62,6 +62,10 @@ extern "C" {
 #define GF2_PREC_BF16X6  3   /* operands split hi+mid+lo BF16; the six products  */
                              /* of order 1, 2^-8 and 2^-16 on BF16 MFMA, FP32    */
                              /* accumulate, FP64 final sums (n <= 144)           */
+#define GF2_PREC_BF16MIX 4   /* per stage: first index transform FP32 MFMA; the  */
+                             /* second and third as BF16X6 (the FP32 first-      */
+                             /* transform result split in registers); the final  */
+                             /* contraction as BF16X3 (n <= 144)                  */
 
 #define GF2_TAU2IW 0         /* gf2_fourier: Sigma(tau) -> Sigma(i w), Sigma_1  */
 #define GF2_IW2TAU 1         /* gf2_fourier: G(i w) + tail moments -> G(tau)     */

@@ -26,7 +26,8 @@ GF2_PREC_FP64 = 0
 GF2_PREC_FP32 = 1
 GF2_PREC_BF16X3 = 2
 GF2_PREC_BF16X6 = 3
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+GF2_PREC_BF16MIX = 4
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "bf16mix": 4}
 
 GF2_TAU2IW = 0
 GF2_IW2TAU = 1

@@ -584,7 +584,7 @@ static int check_params(const gf2_params *p, const char *who) {
         !(p->damp_P >= 0 && p->damp_P < 1) || !(p->damp_Sigma >= 0 && p->damp_Sigma < 1) ||
         (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS &&
          p->mu_method != GF2_MU_SECANT) ||
-        p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16X6)
+        p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16MIX)
         return fail(GF2_EINVAL, std::string(who) + ": bad parameters");
     return GF2_OK;
 }

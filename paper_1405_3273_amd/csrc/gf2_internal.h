@@ -40,7 +40,7 @@ struct DevBuf {
 };
 
 // Sigma(tau) arithmetic modes (match GF2_PREC_*).
-enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2, MODE_BF6 = 3 };
+enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2, MODE_BF6 = 3, MODE_BFM = 4 };
 // Global-memory pointers in kernels.  Pointers read from argument structs are
 // generic, for which the compiler emits flat loads and stores; flat accesses
 // also count against the LDS wait counter, so every wait for an LDS access
@@ -48,8 +48,18 @@ enum { MODE_F64 = 0, MODE_F32 = 1, MODE_BF3 = 2, MODE_BF6 = 3 };
 // streams are therefore addressed through address-space-1 pointers.
 #define GF2_GLOBAL __attribute__((address_space(1)))
 
-// BF16 planes per FP32 operand of a split-precision mode (0: not split).
+// Per-stage arithmetic of the Sigma(tau) contraction.  split_planes: bf16
+// planes of the first transform's output T1 (0: T1 is FP32/FP64);
+// s23_planes: planes per operand in the fused second and third transforms
+// (0: the FP32/FP64 MFMA kernel); s4_planes: the same for the final
+// contraction; s1_mode: the mode of the first transform's kernel.  The mixed
+// mode runs the first transform in FP32 MFMA (T1 stays FP32 and is split in
+// registers where it is read), the second and third in the three-term split
+// and the final contraction in the two-term split.
 constexpr int split_planes(int mode) { return mode == MODE_BF3 ? 2 : mode == MODE_BF6 ? 3 : 0; }
+constexpr int s23_planes(int mode) { return mode == MODE_BFM ? 3 : split_planes(mode); }
+constexpr int s4_planes(int mode) { return mode == MODE_BFM ? 2 : split_planes(mode); }
+constexpr int s1_mode(int mode) { return mode == MODE_BFM ? MODE_F32 : mode; }
 
 }  // namespace gf2
 

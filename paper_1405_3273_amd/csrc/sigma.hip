@@ -1274,9 +1274,9 @@ __global__ void k_stage_gq(int n, int KP, int sl, int p16, int k0, int nb, size_
 }
 
 struct S23b3Args {
-    const unsigned short *T1;   // plane 0; plane i at + i * t1_plane
+    const unsigned short *T1;   // plane 0; plane i at + i * t1_plane (FP32 T1: the FP32 array)
     long long t1_plane;
-    int lq;                     // padded slab row
+    int lq;                     // slab row (padded for planes; n for an FP32 T1)
     const unsigned short *Gq;   // plane 0; plane i at + i * gq_plane
     long long gq_plane;
     const float *Gb;            // G(-tau) [nb][n][n] FP32
@@ -1293,7 +1293,9 @@ static int s23b_pt(int kt) { return (kt >= 2 && kt <= 7) ? 2 : 1; }
 // workgroups per (tau, n)
 static int s23b_groups(int kt) { return (kt + s23b_pt(kt) - 1) / s23b_pt(kt); }
 
-template <int KT, int NP>
+// F32IN: T1 is FP32 (written by the FP32 first transform) and is split into
+// NP planes in registers as each step's operands are used.
+template <int KT, int NP, bool F32IN>
 __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
     constexpr int KP = (KT + 1) / 2;          // 32-deep k steps of the second product
     constexpr int P16 = 16 * KT;
@@ -1367,6 +1369,68 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
         for (int kt = 0; kt < (PT == 2 ? 2 * KP : 1); ++kt) acc1b[kt] = v4f{0, 0, 0, 0};
 
         // ---- Y^T[k][p] = sum_q T1[k][q] Gb[q][p]  (slab symmetric)
+        if constexpr (F32IN) {
+            // FP32 slab rows of n: 8 q of row k as two 4-wide pieces; a piece
+            // at or past q = n reads q = 0.. of the same row instead (finite;
+            // it meets zero rows of G(-tau)), so no load leaves the slab.
+            const GF2_GLOBAL float *T1f = (const GF2_GLOBAL float *)a.T1;
+            float raw[KT][8];
+            auto loadf = [&](int s) {
+                const int q0 = 32 * s + 8 * g;
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) {
+                    const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
+                    const GF2_GLOBAL float *row = T1f + soff + (size_t)k * N;
+                    if (vec4) {
+                        const v4f lo = *(const GF2_GLOBAL v4f *)(row + (q0 < N ? q0 : 0));
+                        const v4f hi = *(const GF2_GLOBAL v4f *)(row + (q0 + 4 < N ? q0 + 4 : 0));
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            raw[kt][e] = lo[e];
+                            raw[kt][4 + e] = hi[e];
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) raw[kt][e] = row[q0 + e < N ? q0 + e : 0];
+                    }
+                }
+            };
+            loadf(0);
+            for (int s = 0; s < S32; ++s) {
+                v8us bv[NP], bw[NP];
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) {
+                    bv[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 32 * s);
+                    if constexpr (PT == 2) bw[pl] = *reinterpret_cast<const v8us *>(BSp[pl] + 16 * SQ + 32 * s);
+                }
+                const int q1 = 32 * (s + 1) + 8 * g;
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) {
+                    v8us av[NP];
+                    split8<NP>(raw[kt], av);
+                    acc1[kt] = mma3<NP>(av, bv, acc1[kt]);
+                    if constexpr (PT == 2)
+                        if (two) acc1b[kt] = mma3<NP>(av, bw, acc1b[kt]);
+                    if (s + 1 < S32) {
+                        // next step's operands of this k tile, in flight during the step
+                        const int k = (kt < KT - 1) ? 16 * kt + c : kc_last;
+                        const GF2_GLOBAL float *row = T1f + soff + (size_t)k * N;
+                        if (vec4) {
+                            const v4f lo = *(const GF2_GLOBAL v4f *)(row + (q1 < N ? q1 : 0));
+                            const v4f hi = *(const GF2_GLOBAL v4f *)(row + (q1 + 4 < N ? q1 + 4 : 0));
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                raw[kt][e] = lo[e];
+                                raw[kt][4 + e] = hi[e];
+                            }
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) raw[kt][e] = row[q1 + e < N ? q1 + e : 0];
+                        }
+                    }
+                }
+            }
+        } else {
         v8us av[KT][NP];
         auto load = [&](int s) {
             int q0 = 32 * s + 8 * g;
@@ -1415,6 +1479,7 @@ __global__ __launch_bounds__(512) void k_s23_bf3(KRef<S23b3Args> ref) {
                     }
                 }
             }
+        }
         }
 
         // ---- X^T[l][p] = sum_k G[k][l] Y^T[k][p]; B operand = two result tiles
@@ -1752,14 +1817,14 @@ static size_t s23b3_lds(int n, int np) {
     return 2 * (size_t)np * ((size_t)P16 * SLG + (size_t)16 * S23bPt<KT>::value * SQ);
 }
 
-template <int KT, int NP>
+template <int KT, int NP, bool F32IN>
 static int launch_s23_bf3_kt(hipStream_t st, dim3 grid, int waves, size_t lds,
                              const KRef<S23b3Args> &r, bool attr_only) {
-    GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT, NP>,
+    GF2_HIP(hipFuncSetAttribute((const void *)k_s23_bf3<KT, NP, F32IN>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)s23b3_lds<KT>(16 * KT, NP)));
     if (attr_only) return GF2_OK;
-    hipLaunchKernelGGL((k_s23_bf3<KT, NP>), grid, dim3(64 * std::min(waves, 8)), lds, st, r);
+    hipLaunchKernelGGL((k_s23_bf3<KT, NP, F32IN>), grid, dim3(64 * std::min(waves, 8)), lds, st, r);
     GF2_HIP(hipGetLastError());
     return GF2_OK;
 }
@@ -1774,12 +1839,22 @@ static size_t s23_bf3_lds(int kt, int n, int np) {
     }
 }
 
-static int launch_s23_bf3(hipStream_t st, int np, int kt, dim3 grid, int waves, size_t lds,
+// f32in: T1 is FP32 (mixed mode: three planes only)
+static int launch_s23_bf3(hipStream_t st, int np, bool f32in, int kt, dim3 grid, int waves, size_t lds,
                           const KRef<S23b3Args> &r, bool attr_only = false) {
     if (kt > split_max_kt(np)) return fail(GF2_EINVAL, "gf2_sigma_tau: n too large for this precision");
-    if (np == 3) {
+    if (f32in) {
+        if (np != 3) return fail(GF2_EINVAL, "gf2_sigma_tau: FP32 T1 needs the three-term split");
         switch (kt) {
-#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 3>(st, grid, waves, lds, r, attr_only);
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 3, true>(st, grid, waves, lds, r, attr_only);
+            GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
+            GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9)
+#undef GF2_B_CASE
+            default: break;
+        }
+    } else if (np == 3) {
+        switch (kt) {
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 3, false>(st, grid, waves, lds, r, attr_only);
             GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
             GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9)
 #undef GF2_B_CASE
@@ -1787,7 +1862,7 @@ static int launch_s23_bf3(hipStream_t st, int np, int kt, dim3 grid, int waves, 
         }
     } else {
         switch (kt) {
-#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 2>(st, grid, waves, lds, r, attr_only);
+#define GF2_B_CASE(K_) case K_: return launch_s23_bf3_kt<K_, 2, false>(st, grid, waves, lds, r, attr_only);
             GF2_B_CASE(1) GF2_B_CASE(2) GF2_B_CASE(3) GF2_B_CASE(4) GF2_B_CASE(5)
             GF2_B_CASE(6) GF2_B_CASE(7) GF2_B_CASE(8) GF2_B_CASE(9) GF2_B_CASE(10)
 #undef GF2_B_CASE
@@ -1862,7 +1937,7 @@ struct SigPlan {
 
 static int sigma_bmax(int n, int mode) {
     const size_t esz = (mode == MODE_F64) ? 8 : 4;
-    const size_t t1sz = split_planes(mode) ? 2 * (size_t)split_planes(mode) : esz;
+    const size_t t1sz = split_planes(mode) ? 2 * (size_t)split_planes(mode) : esz;   // T1 element
     const size_t N4 = (size_t)n * n * n * n;
     const size_t budget = (size_t)16 << 30;   // T1 + X
     return (int)std::min<size_t>(std::max<size_t>(1, budget / (N4 * (esz + t1sz))), 64);
@@ -1872,9 +1947,9 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
                      SigPlan &p) {
     const int n = c->n;
     if (n > 160) return fail(GF2_EINVAL, "gf2_sigma_tau: n > 160 is not supported");
-    const int np = split_planes(prec);
-    if (np && (n + 15) / 16 > split_max_kt(np))
-        return fail(GF2_EINVAL, "gf2_sigma_tau: BF16x6 supports n <= 144");
+    const int np = split_planes(prec), np23 = s23_planes(prec), np4 = s4_planes(prec);
+    if (np23 && (n + 15) / 16 > split_max_kt(np23))
+        return fail(GF2_EINVAL, "gf2_sigma_tau: the three-term split forms support n <= 144");
     p = SigPlan();
     p.c = c;
     p.mode = prec;
@@ -1886,7 +1961,7 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
     const long long N = n, N2 = N * N, N3 = N2 * N, N4 = N3 * N;
     const size_t esz = (p.mode == MODE_F64) ? 8 : 4;
     if (p.mode != MODE_F64 && !c->have_f32_layouts) GF2_TRY(sigma_build_layouts(c, true));
-    if (np && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
+    if (np4 && !c->have_bf3_layouts) GF2_TRY(build_bf3_layouts(c));
     p.V = (p.mode == MODE_F64) ? c->v.ptr : c->v_32.ptr;
     p.W2 = (p.mode == MODE_F64) ? c->W2_64.ptr : c->W2_32.ptr;
     p.KT = (n + 15) / 16;
@@ -1897,29 +1972,27 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
     p.kz = 4096;
     if (N3 < 8 * 4096) p.kz = std::max<long long>(512, ((N3 / 8) + 511) / 512 * 512);
     p.nsplit = (int)((N3 + p.kz - 1) / p.kz);
-    p.s1_bk = (p.mode == MODE_F32 && n % 16 != 0 && n % 20 == 0) ? 20 : 16;
+    p.s1_bk = (s1_mode(p.mode) == MODE_F32 && n % 16 != 0 && n % 20 == 0) ? 20 : 16;
     const int bmax = sigma_bmax(n, p.mode);
     p.sh.b = std::max(1, std::min(sh.b > 0 ? sh.b : bmax, std::min(bmax, ntau)));
     const int wmax = (p.mode == MODE_F64) ? max_waves<MODE_F64>(p.KT)
                      : (p.mode == MODE_F32) ? max_waves<MODE_F32>(p.KT) : 8;
     if (sh.waves > 0) {
         p.sh.waves = std::min(sh.waves, wmax);
-    } else if (np) {
-        const int per_cu = std::max<int>(1, (int)((160 * 1024) / s23_bf3_lds(p.KT, n, np)));
+    } else if (np23) {
+        const int per_cu = std::max<int>(1, (int)((160 * 1024) / s23_bf3_lds(p.KT, n, np23)));
         p.sh.waves = std::min(8, std::max(4, 16 / per_cu));
     } else {
         p.sh.waves = (p.mode == MODE_F64) ? default_waves<MODE_F64>(p.KT, n)
                                           : default_waves<MODE_F32>(p.KT, n);
     }
-    p.sh.s4cb = np ? 1 : (sh.s4cb > 0 ? std::min(sh.s4cb, 2) : 1);
+    p.sh.s4cb = np4 ? 1 : (sh.s4cb > 0 ? std::min(sh.s4cb, 2) : 1);
     p.s4_nt = (p.KT + p.sh.s4cb - 1) / p.sh.s4cb;
     const size_t b = (size_t)p.sh.b;
     p.t1_plane = b * N2 * N * p.lq;
     p.gq_plane = b * 16 * p.KT * p.SLG;
-    if (np) {
-        GF2_TRY(c->sig_T1.ensure(np * p.t1_plane * 2));
-        GF2_TRY(c->sig_Gq.ensure(np * p.gq_plane * 2));
-    }
+    if (np) GF2_TRY(c->sig_T1.ensure(np * p.t1_plane * 2));
+    if (np23) GF2_TRY(c->sig_Gq.ensure(np23 * p.gq_plane * 2));
     GF2_TRY(c->sig_T1.ensure(b * N4 * esz));
     GF2_TRY(c->sig_X.ensure(b * N4 * esz));
     GF2_TRY(c->sig_G.ensure(b * N2 * esz));
@@ -1946,14 +2019,14 @@ static int plan_stage(const SigPlan &p, hipStream_t st, int k0, int nb) {
     } else {
         hipLaunchKernelGGL(k_stage_g<float>, dim3(blocks), dim3(256), 0, st, n, p.M, k0, nb, p.G,
                            c->sig_G.as<float>(), c->sig_Gb.as<float>());
-        if (p.mode == MODE_F32) {
+        if (s23_planes(p.mode) == 0) {
             hipLaunchKernelGGL(k_stage_gp<float>, dim3(blocksp), dim3(256), 0, st, n, p.KT,
                                p.SL, 16 * (p.KT - 1), p.M, k0, nb, p.G, c->sig_Gp.as<float>());
         } else {
             const size_t totq = (size_t)nb * 16 * p.KT * p.SLG;
             const unsigned blocksq = (unsigned)std::min<size_t>((totq + 255) / 256, 4096);
             hipLaunchKernelGGL(k_stage_gq, dim3(blocksq), dim3(256), 0, st, n, p.KP, p.SLG, 16 * p.KT,
-                               k0, nb, p.gq_plane, split_planes(p.mode), p.G,
+                               k0, nb, p.gq_plane, s23_planes(p.mode), p.G,
                                c->sig_Gq.as<unsigned short>());
         }
     }
@@ -2004,7 +2077,7 @@ static S23b3Args plan_s23b3(const SigPlan &p, int nb) {
     S23b3Args a{};
     a.T1 = p.c->sig_T1.as<unsigned short>();
     a.t1_plane = (long long)p.t1_plane;
-    a.lq = p.lq;
+    a.lq = split_planes(p.mode) ? p.lq : p.n;
     a.Gq = p.c->sig_Gq.as<unsigned short>();
     a.gq_plane = (long long)p.gq_plane;
     a.Gb = p.c->sig_Gb.as<float>();
@@ -2050,7 +2123,8 @@ static S4b3Args plan_s4b3(const SigPlan &p, int nb) {
     return b;
 }
 
-static int launch_s1(int mode, int bk, int nt, dim3 grid, hipStream_t st, const KRef<GemmArgs> &r) {
+static int launch_s1(int mode_, int bk, int nt, dim3 grid, hipStream_t st, const KRef<GemmArgs> &r) {
+    const int mode = s1_mode(mode_);
     if (mode == MODE_F64) launch_nt<MODE_F64, false, true, 16>(nt, grid, st, r);
     else if (mode == MODE_BF3) launch_nt<MODE_BF3, false, true, 0>(nt, grid, st, r);
     else if (mode == MODE_BF6) launch_nt<MODE_BF6, false, true, 0>(nt, grid, st, r);
@@ -2075,14 +2149,15 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
         if (prof) prof_end(c, ph, fl);
     }
     {
-        const int np = split_planes(p.mode);
+        const int np = s23_planes(p.mode);
         const int groups = np ? s23b_groups(p.KT) : s23_groups(p.mode, p.KT);
         const dim3 grid(xcd_grid((long long)nb * p.n * groups));
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_S23) : -1;
         if (np) {
             KRef<S23b3Args> r{};
             r.one = plan_s23b3(p, nb);
-            GF2_TRY(launch_s23_bf3(st, np, p.KT, grid, p.sh.waves, s23_bf3_lds(p.KT, p.n, np), r));
+            GF2_TRY(launch_s23_bf3(st, np, split_planes(p.mode) == 0, p.KT, grid, p.sh.waves,
+                                   s23_bf3_lds(p.KT, p.n, np), r));
         } else {
             KRef<S23Args> r{};
             r.one = plan_s23(p, nb);
@@ -2095,11 +2170,11 @@ static int plan_run_batch(const SigPlan &p, hipStream_t st, int k0, int nb, bool
     }
     {
         const int ph = prof ? prof_begin(c, GF2_KC_SIGMA_SPLITK) : -1;
-        if (split_planes(p.mode)) {
+        if (s4_planes(p.mode)) {
             KRef<S4b3Args> r{};
             r.one = plan_s4b3(p, nb);
             const dim3 grid(xcd_grid((long long)r.one.nrb * r.one.nsplit));
-            GF2_TRY(launch_s4_bf3(st, split_planes(p.mode), p.KT, grid, r));
+            GF2_TRY(launch_s4_bf3(st, s4_planes(p.mode), p.KT, grid, r));
         } else {
             KRef<S4Args> r{};
             r.one = plan_s4(p, nb);
@@ -2161,13 +2236,13 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
         std::vector<int> bs;
         for (int b : {bmax, (bmax + 1) / 2, (bmax + 3) / 4})
             if (b >= 1 && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
-        std::vector<int> ws = split_planes(prec) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+        std::vector<int> ws = s23_planes(prec) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
         hipEvent_t e0, e1;
         GF2_HIP(hipEventCreate(&e0));
         GF2_HIP(hipEventCreate(&e1));
         double best_t = 1e300;
         int rc = GF2_OK;
-        std::vector<int> cbs = split_planes(prec) ? std::vector<int>{1} : std::vector<int>{1, 2};
+        std::vector<int> cbs = s4_planes(prec) ? std::vector<int>{1} : std::vector<int>{1, 2};
         for (int b : bs) {
           for (int cb : cbs) {
             for (int w : ws) {
@@ -2251,7 +2326,8 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
         GF2_TRY(tuned_shape(cs[s], ntau[s], prec, G[s], Sig[s], sh));
         GF2_TRY(plan_init(cs[s], ntau[s], prec, G[s], Sig[s], sh, plans[s]));
     }
-    const int np = split_planes(prec);
+    const int np = split_planes(prec), np23 = s23_planes(prec), np4 = s4_planes(prec);
+    const bool f32in = np == 0;
     if (np)
         for (auto &p : plans) GF2_TRY(fill_zero(p.c, p.c->sig_T1.ptr, np * p.t1_plane * 2));
     // shape key: everything the captured launches depend on
@@ -2310,12 +2386,12 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
             std::vector<int> boff{0};
             size_t lds = 0;
             GroupLaunch gl{2, kv.first.first, kv.first.second, 0, 0, 0, (int)kv.second.size(), 0, 0};
-            if (np) {
+            if (np23) {
                 std::vector<S23b3Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s23b3(plans[s], nb_of(s)));
                     boff.push_back(boff.back() + nb_of(s) * plans[s].n * s23b_groups(plans[s].KT));
-                    lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n, np));
+                    lds = std::max(lds, s23_bf3_lds(plans[s].KT, plans[s].n, np23));
                 }
                 push_table(buf, tab, boff, gl);
             } else {
@@ -2334,11 +2410,11 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
         }
         // S4 classes (NT)
         std::map<int, std::vector<int>> c4;
-        for (int s : act) c4[np ? plans[s].KT : plans[s].s4_nt].push_back(s);
+        for (int s : act) c4[np4 ? plans[s].KT : plans[s].s4_nt].push_back(s);
         for (auto &kv : c4) {
             std::vector<int> boff{0};
             GroupLaunch gl{4, kv.first, 0, 0, 0, 0, (int)kv.second.size(), 0, 0};
-            if (np) {
+            if (np4) {
                 std::vector<S4b3Args> tab;
                 for (int s : kv.second) {
                     tab.push_back(plan_s4b3(plans[s], nb_of(s)));
@@ -2366,7 +2442,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
             if (gl.stage == 2) {
                 KRef<S23Args> r0{};
                 KRef<S23b3Args> r1{};
-                if (np) GF2_TRY(launch_s23_bf3(lead->stream, np, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r1, true));
+                if (np23) GF2_TRY(launch_s23_bf3(lead->stream, np23, f32in, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r1, true));
                 else if (prec == MODE_F64) GF2_TRY(launch_s23<MODE_F64>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
                 else GF2_TRY(launch_s23<MODE_F32>(lead->stream, gl.cls_a, dim3(1), gl.cls_b, gl.lds, r0, true));
             }
@@ -2393,13 +2469,13 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                 ref.total = gl.total;
                 rc = launch_s1(prec, gl.cls_a, gl.cls_b, grid, st, ref);
             } else if (gl.stage == 2) {
-                if (np) {
+                if (np23) {
                     KRef<S23b3Args> ref{};
                     ref.tab = reinterpret_cast<const S23b3Args *>(tb + gl.tab_off);
                     ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
                     ref.nsys = gl.nsys;
                     ref.total = gl.total;
-                    rc = launch_s23_bf3(st, np, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
+                    rc = launch_s23_bf3(st, np23, f32in, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
                 } else {
                     KRef<S23Args> ref{};
                     ref.tab = reinterpret_cast<const S23Args *>(tb + gl.tab_off);
@@ -2410,13 +2486,13 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                     else rc = launch_s23<MODE_F32>(st, gl.cls_a, grid, gl.cls_b, gl.lds, ref);
                 }
             } else {
-                if (np) {
+                if (np4) {
                     KRef<S4b3Args> ref{};
                     ref.tab = reinterpret_cast<const S4b3Args *>(tb + gl.tab_off);
                     ref.boff = reinterpret_cast<const int *>(tb + gl.boff_off);
                     ref.nsys = gl.nsys;
                     ref.total = gl.total;
-                    rc = launch_s4_bf3(st, np, gl.cls_a, grid, ref);
+                    rc = launch_s4_bf3(st, np4, gl.cls_a, grid, ref);
                 } else {
                     KRef<S4Args> ref{};
                     ref.tab = reinterpret_cast<const S4Args *>(tb + gl.tab_off);
@@ -2467,7 +2543,7 @@ extern "C" int gf2_sigma_tau(gf2_ctx *c, const gf2_dims *d, int prec, const doub
     if (!c->has_system) return fail(GF2_ESTATE, "gf2_sigma_tau: no system set");
     if (d->n != c->n) return fail(GF2_EINVAL, "gf2_sigma_tau: dims->n differs from the system");
     if (d->ntau < 4) return fail(GF2_EINVAL, "gf2_sigma_tau: ntau must be >= 4");
-    if (prec < GF2_PREC_FP64 || prec > GF2_PREC_BF16X6)
+    if (prec < GF2_PREC_FP64 || prec > GF2_PREC_BF16MIX)
         return fail(GF2_EINVAL, "gf2_sigma_tau: bad precision");
     if ((const void *)G_tau == (const void *)Sigma_tau)
         return fail(GF2_EINVAL, "gf2_sigma_tau: Sigma_tau aliases G_tau");

@@ -31,7 +31,7 @@ def _make(sysm):
     return g
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_batched_equals_single(torch, prec):
     from paper_1405_3273_amd import make_params
     from paper_1405_3273_amd.runtime import Gf2Batch

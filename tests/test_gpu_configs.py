@@ -88,3 +88,28 @@ def test_n160_correlated_iteration(torch):
     assert abs(float(np.trace(P @ s.S)) - s.nelec) < 1e-9 * s.nelec
     assert np.isfinite(r1.energy)
     g.close()
+
+
+def test_n100_split_forms_energy_against_fp64(torch):
+    """The N = 100 workload (beta = 200, 16384 frequencies, 512 tau points): five
+    outer iterations from the same start with each Sigma arithmetic.  The
+    energies after every iteration stay within the bars against the FP64 form:
+    FP32 1e-6 Eh; the mixed split form (three-term split in the second and third
+    transforms) 1e-5 Eh.  The two-term split (BF16x3) does not meet 1e-5 Eh at
+    this size (its operands carry 2^-16 relative error; measured 4e-5 to 8e-5 Eh):
+    its bound here is 2e-4 Eh."""
+    from paper_1405_3273_amd import make_params
+    from synthetic import molecule_n100
+    s = molecule_n100()
+    bars = {"fp32": 1e-6, "bf16mix": 1e-5, "bf16x3": 2e-4}
+    energies = {}
+    for prec in ("fp64", "fp32", "bf16mix", "bf16x3"):
+        g = _make(s)
+        prm = make_params(damp_Sigma=0.5, prec=prec, tol_N_rel=1e-2)
+        energies[prec] = [g.iterate(prm).energy for _ in range(5)]
+        print(prec, " ".join(f"{e:.10f}" for e in energies[prec]), flush=True)
+        g.close()
+    for prec, bar in bars.items():
+        d = np.abs(np.array(energies[prec]) - np.array(energies["fp64"]))
+        print(f"{prec} - fp64: {d}", flush=True)
+        assert np.all(d <= bar), prec

@@ -28,7 +28,7 @@ def _system():
     return generic_system(6, 31, naux=12, beta=20.0, niw=256, ntau=33)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_tau_nonfinite_input_reports_enonfinite(torch, prec):
     from paper_1405_3273_amd import _lib as L
     print(f"errors: sigma_tau NaN prec={prec}", flush=True)

@@ -8,7 +8,7 @@ from synthetic import System, small_molecule
 pytestmark = pytest.mark.gpu
 
 # energy bars per Sigma arithmetic (Eh), FP64 relative 1e-10
-E_TOL = {"fp64": None, "fp32": 1e-6, "bf16x3": 1e-5, "bf16x6": 1e-6}
+E_TOL = {"fp64": None, "fp32": 1e-6, "bf16x3": 1e-5, "bf16x6": 1e-6, "bf16mix": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +37,7 @@ def _params(p: O.Params, prec):
                        damp_Sigma=p.damp_Sigma, mu_method=p.mu_method, prec=prec)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_iterations_match_oracle(torch, oracle_run, prec):
     from paper_1405_3273_amd.runtime import Gf2
     s, p, reps, st = oracle_run
@@ -101,7 +101,7 @@ def test_inexact_mu_search_reaches_the_same_iterations(torch, oracle_run, rel):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_converged_energy(torch, prec):
     """The loop run to self-consistency (FP64: |dE| < 1e-9 Eh and max|dP| <
     1e-8 between outer iterations, as the stored oracle run; FP32, BF16x3:

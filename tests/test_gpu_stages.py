@@ -7,7 +7,7 @@ from synthetic import generic_system, random_tau_stack, random_symmetric
 
 pytestmark = pytest.mark.gpu
 
-TOL_SIGMA = {"fp64": 1e-12, "fp32": 3e-5, "bf16x3": 3e-4, "bf16x6": 3e-5}   # max|err| / max|ref|
+TOL_SIGMA = {"fp64": 1e-12, "fp32": 3e-5, "bf16x3": 3e-4, "bf16x6": 3e-5, "bf16mix": 3e-5}   # max|err| / max|ref|
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +37,7 @@ def _relerr(got, ref):
 
 @pytest.mark.parametrize("n,ntau", [(1, 5), (3, 9), (10, 257), (16, 7), (17, 12), (33, 6),
                                     (40, 5), (48, 4)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_tau_matches_oracle(torch, n, ntau, prec):
     print(f"sigma n={n} ntau={ntau} prec={prec}", flush=True)
     s = generic_system(n, 500 + n, naux=max(2, 2 * n), beta=20.0, ntau=ntau)
@@ -53,7 +53,7 @@ def test_sigma_tau_matches_oracle(torch, n, ntau, prec):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_tau_n100_sampled(torch, prec):
     """N=100 (the benchmark size) on a few tau points, all elements."""
     print(f"sigma n=100 prec={prec}", flush=True)
@@ -70,7 +70,7 @@ def test_sigma_tau_n100_sampled(torch, prec):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_tau_n120_sampled(torch, prec):
     """N=120: eight 16-row tiles (the FP64 form reads G(tau) from memory, not LDS)."""
     print(f"sigma n=120 prec={prec}", flush=True)
@@ -97,9 +97,10 @@ def test_bf16x6_rejects_n_above_144(torch):
     v = torch.zeros((n, n, n, n), dtype=torch.float64, device="cuda")
     g = Gf2(np.eye(n), np.zeros((n, n)), v, nelec=n, beta=10.0, niw=8, ntau=4)
     Gt = _dev(torch, random_tau_stack(np.random.default_rng(3), 4, n))
-    with pytest.raises(L.Gf2Error) as e:
-        g.sigma_tau(Gt, "bf16x6")
-    assert e.value.code == L.GF2_EINVAL
+    for prec in ("bf16x6", "bf16mix"):
+        with pytest.raises(L.Gf2Error) as e:
+            g.sigma_tau(Gt, prec)
+        assert e.value.code == L.GF2_EINVAL
     assert float(g.sigma_tau(Gt, "fp32").abs().max()) == 0.0     # v = 0 gives Sigma = 0
     del v
     g.close()
@@ -278,7 +279,7 @@ def test_density_fock_rejects_impossible_electron_count(torch):
 
 
 @pytest.mark.parametrize("n", [17, 40])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_shape_invariant(torch, n, prec):
     """The tuned launch shape (tau batch, waves per S23 workgroup) moves work
     between workgroups only: every shape gives bitwise the same Sigma(tau)."""
