@@ -234,6 +234,70 @@ def run_sweep(args, desc):
     print(json.dumps(line), flush=True)
 
 
+def run_converge(args, sysm, desc):
+    """Run the loop from the core guess to |dE| < tol_E on two consecutive outer
+    iterations.  The reduced-precision Sigma(tau) forms reach a noise floor
+    between iterations (FP32 at N = 160: about 5e-7 Eh); once |dE| falls below
+    --switch-dE, Sigma(tau) runs in --prec-final (the loop state carries over:
+    the iteration simply continues with the other arithmetic)."""
+    import numpy as np
+    import torch
+    from paper_1405_3273_amd import _lib as L
+    from paper_1405_3273_amd.runtime import Gf2
+
+    g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
+            ntau=sysm.ntau)
+    if sysm.tau is not None:
+        g.set_tau_grid(sysm.tau)
+    g.reset(mu0=float(np.mean(np.diag(sysm.h))))
+    prec = args.prec
+    tol_P, tol_N = 1e-10, 1e-10
+    hist = []
+    below = 0
+    switched_at = None
+    t_start = time.perf_counter()
+    for it in range(args.max_outer):
+        prm = L.make_params(prec=prec, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel, tol_P=tol_P,
+                            tol_N=tol_N)
+        r = g.iterate(prm)
+        hist.append({"iteration": it, "prec": prec, "energy": r.energy, "dE": r.dE, "dP": r.dP,
+                     "n_inner": r.n_inner, "n_eval": r.n_eval, "ms": r.ms_total,
+                     "ms_sigma": r.ms_sigma})
+        log(f"iteration {it} [{prec}]: E {r.energy:.10f} dE {r.dE:+.2e} dP {r.dP:.1e} inner "
+            f"{r.n_inner} evals {r.n_eval} {r.ms_total:.0f} ms (sigma {r.ms_sigma:.0f})")
+        if it >= 2 and switched_at is None and abs(r.dE) < args.switch_dE:
+            prec = args.prec_final
+            tol_P, tol_N = args.tol_P_final, min(1e-10, args.tol_P_final)
+            switched_at = it + 1
+            below = 0
+            log(f"|dE| < {args.switch_dE:g}: Sigma(tau) in {prec}, inner tol_P {tol_P:g} from "
+                f"iteration {switched_at}")
+            continue
+        below = below + 1 if (it >= 2 and abs(r.dE) < args.tol_E) else 0
+        if below >= 2:
+            break
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    g.close()
+    line = {
+        "metric": METRIC, "value": len(hist) / elapsed, "unit": "iterations/s", "n_gpus": 1,
+        "steps": len(hist), "warmup": 0, "ms_per_step": elapsed / len(hist) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16",
+                  "bf16mix": "bf16+f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": desc, "mode": "converge", "sigma_arithmetic": args.prec,
+                   "sigma_arithmetic_final": args.prec_final, "switch_dE": args.switch_dE,
+                   "inner_tol_P": 1e-10, "inner_tol_P_final": args.tol_P_final,
+                   "tol_E": args.tol_E, "damp_Sigma": 0.5, "mu_tol_N_rel": args.mu_tol_rel},
+        "convergence": {"converged": below >= 2, "iterations": len(hist),
+                        "switched_at": switched_at, "seconds": elapsed,
+                        "energy": hist[-1]["energy"], "last_dE": [h["dE"] for h in hist[-3:]],
+                        "history": hist},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +316,18 @@ def main():
                     help="other Sigma precisions run through the same iterations from the same\n"
                          "start, for the whole-iteration speedup and energy difference against\n"
                          "the FP64 form ('' to skip)")
+    ap.add_argument("--tau-grid", default="",
+                    help="'L,U': run on the non-equidistant power grid of L halvings with U\n"
+                         "steps each (2 L U + 1 points) instead of the uniform grid")
+    ap.add_argument("--converge", action="store_true",
+                    help="run from the core guess until |dE| < --tol-E twice in a row (no timing\n"
+                         "legs); Sigma(tau) switches to --prec-final once |dE| < --switch-dE")
+    ap.add_argument("--tol-E", type=float, default=1e-7)
+    ap.add_argument("--switch-dE", type=float, default=2e-6)
+    ap.add_argument("--prec-final", default="fp64", choices=["fp64", "fp32", "bf16x6", "bf16mix"])
+    ap.add_argument("--tol-P-final", type=float, default=1e-10,
+                    help="inner-loop max|dP| tolerance from the switch on (1e-10 before)")
+    ap.add_argument("--max-outer", type=int, default=150)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the workload (a kernel of known\n"
                          "traffic, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -281,8 +357,17 @@ def main():
     t0 = time.perf_counter()
     sysm = getattr(synthetic, gen)()
     log(f"workload {desc} generated in {time.perf_counter() - t0:.1f} s")
+    if args.tau_grid:
+        lv, per = (int(x) for x in args.tau_grid.split(","))
+        sysm.tau = synthetic.power_tau_grid(sysm.beta, lv, per)
+        sysm.ntau = len(sysm.tau)
+        desc += f"; power tau grid {lv} x {per} ({sysm.ntau} points)"
+    if args.converge:
+        return run_converge(args, sysm, desc)
     g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
             ntau=sysm.ntau)
+    if sysm.tau is not None:
+        g.set_tau_grid(sysm.tau)
     g.reset(mu0=float(np.mean(np.diag(sysm.h))))
     prm = L.make_params(prec=args.prec, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel)
 
@@ -377,6 +462,8 @@ def main():
     for pr in [p for p in args.forms.split(",") if p and p != args.prec]:
         gf = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
                  ntau=sysm.ntau)
+        if sysm.tau is not None:
+            gf.set_tau_grid(sysm.tau)
         gf.reset(mu0=float(np.mean(np.diag(sysm.h))))
         pf = L.make_params(prec=pr, damp_Sigma=0.5, tol_N_rel=args.mu_tol_rel)
         for w in range(args.warmup):

@@ -109,6 +109,12 @@ typedef struct {
                          /* max|P_out - P_in| of pass k-1)); the inner loop     */
                          /* stops only after a pass that used tol_N.            */
 } gf2_params;
+/* No outer-iteration limit and no determinism switch: gf2_iterate runs one
+ * outer iteration, so the caller owns the outer loop, its limit and its stop
+ * test (tol_E is carried for that caller); and every call is deterministic --
+ * all floating-point reductions (split-K partial sums, per-frequency partial
+ * densities and traces, Fock partials) are added in a fixed order, so equal
+ * inputs give bitwise equal results on every run and every launch shape. */
 
 /* Outer-loop state, owned by the caller (device arrays [..][n][n]). */
 typedef struct {
@@ -139,7 +145,9 @@ typedef struct {
 int gf2_ctx_create(gf2_ctx **ctx, int device, void *stream);
 int gf2_ctx_destroy(gf2_ctx *ctx);
 
-/* Message of the last failure on the calling thread ("" if none). */
+/* Message of the last failure on the calling thread ("" if none).  The
+ * message is per thread, not per context: a thread that drives several
+ * contexts reads it right after the failing call. */
 const char *gf2_last_error(void);
 
 /* gf2_set_system: the one-particle data and integrals of the problem

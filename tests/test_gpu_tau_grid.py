@@ -102,12 +102,15 @@ def test_grid_path_equals_uniform_path_on_a_uniform_grid(torch):
     g.close()
 
 
-def test_workload_size_transforms_sampled(torch):
-    """N = 100, 16384 frequencies, a 513-point power grid: every element is
-    transformed on the GPU; a 3x3 block is checked against the oracle (the
-    transforms act element by element).  Prints the transform times."""
+@pytest.mark.parametrize("levels,per_level", [(8, 32), (12, 160)])
+def test_workload_size_transforms_sampled(torch, levels, per_level):
+    """N = 100, 16384 frequencies, a 513-point power grid and one of 3841 points
+    (the paper's "3000-4000 points"): every element is transformed on the GPU;
+    a 3x3 block is checked against the oracle (the transforms act element by
+    element).  Prints the transform times."""
     n, beta, niw = 100, 200.0, 16384
-    tau = power_tau_grid(beta, 8, 32)
+    tau = power_tau_grid(beta, levels, per_level)
+    print(f"grid {levels}x{per_level}: {len(tau)} points", flush=True)
     rng = np.random.default_rng(11)
     Y = random_tau_stack(rng, len(tau), n)
     G = _random_giw(rng, niw, 3, beta)
