@@ -155,6 +155,38 @@ __device__ __forceinline__ void split_bf16n(float x, unsigned short (&o)[NP]) {
     }
 }
 
+// The same split for two values at once, one 32-bit word per plane (x0's term
+// in the low half, x1's in the high half: two consecutive elements of a bf16
+// vector).  One v_cvt_pk_bf16_f32 rounds both (nearest even, as the scalar
+// conversion), and the terms return to FP32 by a shift or a mask, so the planes
+// are bitwise those of split_bf16n at half the instructions.
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
+template <int NP>
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned (&w)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const unsigned u = __builtin_bit_cast(unsigned, __builtin_convertvector(v2f_t{x0, x1}, v2bf_t));
+        w[i] = u;
+        if (i + 1 < NP) {
+            x0 -= __uint_as_float(u << 16);
+            x1 -= __uint_as_float(u & 0xffff0000u);
+        }
+    }
+}
+
+// Eight values into NP bf16 vectors of 8 (one per plane).
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+template <int NP>
+__device__ __forceinline__ void split8(const float (&x)[8], v8us (&o)[NP]) {
+    unsigned w[4][NP];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split_pair<NP>(x[2 * e], x[2 * e + 1], w[e]);
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl)
+        o[pl] = __builtin_bit_cast(v8us, v4u_t{w[0][pl], w[1][pl], w[2][pl], w[3][pl]});
+}
+
 template <class T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 
 // ---------------------------------------------------------------------------
@@ -429,14 +461,11 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
     auto store_chunk = [&]() {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            float x8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x8[e] = ra[h * 8 + e];
             v8us t[NP];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                unsigned short o[NP];
-                split_bf16n<NP>(ra[h * 8 + e], o);
-#pragma unroll
-                for (int pl = 0; pl < NP; ++pl) t[pl][e] = o[pl];
-            }
+            split8<NP>(x8, t);
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl)
                 *reinterpret_cast<v8us *>(&As[pl][a_m][a_k0 + h * 8]) = t[pl];
@@ -447,13 +476,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf3(KRef<GemmArgs> r) {
             if (grp < BG) {
                 const int n = grp % BN, kg = grp / BN;
                 v8us t[NP];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    unsigned short o[NP];
-                    split_bf16n<NP>(rb[it][e], o);
-#pragma unroll
-                    for (int pl = 0; pl < NP; ++pl) t[pl][e] = o[pl];
-                }
+                split8<NP>(rb[it], t);
 #pragma unroll
                 for (int pl = 0; pl < NP; ++pl)
                     *reinterpret_cast<v8us *>(&Bs[pl][n][kg * 8]) = t[pl];
@@ -1217,16 +1240,6 @@ typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ v8bf_t as_bf8(v8us x) { return __builtin_bit_cast(v8bf_t, x); }
 
-template <int NP>
-__device__ __forceinline__ void split8(const float (&x)[8], v8us (&o)[NP]) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        unsigned short t[NP];
-        split_bf16n<NP>(x[e], t);
-#pragma unroll
-        for (int pl = 0; pl < NP; ++pl) o[pl][e] = t[pl];
-    }
-}
 
 template <int NP>
 __device__ __forceinline__ v4f mma3(const v8us (&a)[NP], const v8us (&b)[NP], v4f acc) {
