@@ -298,6 +298,61 @@ def run_converge(args, sysm, desc):
     print(json.dumps(line), flush=True)
 
 
+def run_beta_scan(args, desc):
+    """Temperature dependence of the converged GF2 state of the N=10 system: the loop
+    run to |dE| < 1e-9 Eh and max|dP| < 1e-8 (FP64 Sigma) at each inverse temperature,
+    with the Matsubara cutoff (2 n_w + 1) pi / beta and the tau step beta / (n_tau - 1) of
+    the beta = 50 workload kept fixed.  Reports E(T), mu(T), the natural occupations
+    and the heat capacity C = dE/dT by central differences in T."""
+    import numpy as np
+    import torch
+    import synthetic
+    from paper_1405_3273_amd import _lib as L
+    from paper_1405_3273_amd.runtime import Gf2
+
+    rows = []
+    t_start = time.perf_counter()
+    total_it = 0
+    for beta in [float(b) for b in args.betas.split(",")]:
+        s = synthetic.small_molecule()
+        scale = beta / 50.0
+        s.beta, s.niw, s.ntau = beta, int(round(2048 * scale)), int(round(256 * scale)) + 1
+        g = Gf2(s.S, s.h, s.v, nelec=s.nelec, beta=s.beta, niw=s.niw, ntau=s.ntau)
+        g.reset(mu0=-1.0)
+        prm = L.make_params(prec="fp64", damp_Sigma=0.5)
+        conv = False
+        for it in range(200):
+            r = g.iterate(prm)
+            total_it += 1
+            if it > 1 and abs(r.dE) < 1e-9 and r.dP < 1e-8:
+                conv = True
+                break
+        occ = g.natural_occupations(g.P).cpu().numpy()
+        rows.append({"beta": beta, "T": 1.0 / beta, "niw": s.niw, "ntau": s.ntau, "converged": conv,
+                     "iterations": it + 1, "energy": r.energy, "e1b": r.e1b, "e2b": r.e2b, "mu": r.mu,
+                     "occupations": [float(x) for x in occ]})
+        log(f"beta {beta:g}: {it + 1} iterations, E {r.energy:.10f} (E_2b {r.e2b:.8f}), mu {r.mu:.8f}, "
+            f"NONs {occ[0]:.6f} .. {occ[-1]:.6f}")
+        g.close()
+    elapsed = time.perf_counter() - t_start
+    T = np.array([r["T"] for r in rows])
+    E = np.array([r["energy"] for r in rows])
+    order = np.argsort(T)
+    for a in range(1, len(order) - 1):
+        i0, i1, i2 = order[a - 1], order[a], order[a + 1]
+        rows[i1]["heat_capacity"] = float((E[i2] - E[i0]) / (T[i2] - T[i0]))
+    line = {
+        "metric": METRIC, "value": total_it / elapsed, "unit": "iterations/s", "n_gpus": 1,
+        "steps": total_it, "warmup": 0, "ms_per_step": elapsed / total_it * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "mode": "beta scan (converged at each temperature)",
+                   "betas": args.betas, "sigma_arithmetic": "fp64", "damp_Sigma": 0.5},
+        "temperature_dependence": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +371,9 @@ def main():
                     help="other Sigma precisions run through the same iterations from the same\n"
                          "start, for the whole-iteration speedup and energy difference against\n"
                          "the FP64 form ('' to skip)")
+    ap.add_argument("--beta-scan", action="store_true",
+                    help="N=10 system converged at each of --betas (temperature dependence)")
+    ap.add_argument("--betas", default="25,37.5,50,75,100,150,200")
     ap.add_argument("--tau-grid", default="",
                     help="'L,U': run on the non-equidistant power grid of L halvings with U\n"
                          "steps each (2 L U + 1 points) instead of the uniform grid")
@@ -352,6 +410,8 @@ def main():
         del a, b
 
     gen, desc = WORKLOADS[args.workload]
+    if args.beta_scan:
+        return run_beta_scan(args, WORKLOADS["n10"][1].split(",")[0] + " system (N=10, seed 0)")
     if args.workload == "c2":
         return run_sweep(args, desc)
     t0 = time.perf_counter()

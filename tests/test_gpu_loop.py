@@ -137,3 +137,26 @@ def test_converged_energy(torch, prec):
     else:
         assert abs(r.energy - gold["energy"]) <= E_TOL[prec]
     g.close()
+
+
+@pytest.mark.parametrize("beta", [25.0, 100.0])
+def test_iterations_match_oracle_at_other_temperatures(torch, beta):
+    """The N=10 system at another inverse temperature (Matsubara cutoff and tau step
+    of the beta = 50 workload kept, as bench.py --beta-scan runs it): the Hartree-Fock
+    reference and two correlated iterations (FP64 Sigma) against the oracle's loop."""
+    from paper_1405_3273_amd.runtime import Gf2
+    s = small_molecule()
+    scale = beta / 50.0
+    s.beta, s.niw, s.ntau = beta, int(round(2048 * scale)), int(round(256 * scale)) + 1
+    p = O.Params(damp_Sigma=0.5)
+    st = O.State(mu=-1.0, F=s.h.copy())
+    refs = [O.outer_iteration(s, p, st) for _ in range(3)]
+    g = Gf2(s.S, s.h, s.v, nelec=s.nelec, beta=s.beta, niw=s.niw, ntau=s.ntau)
+    g.reset(mu0=-1.0)
+    prm = _params(p, "fp64")
+    for it, ref in enumerate(refs):
+        r = g.iterate(prm)
+        print(f"beta {beta:g} it {it}: E {r.energy:.12f} / {ref.energy:.12f} mu {r.mu:.10f}", flush=True)
+        assert r.energy == pytest.approx(ref.energy, rel=1e-10)
+        assert r.mu == pytest.approx(ref.mu, abs=1e-9)
+    g.close()
