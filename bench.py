@@ -353,6 +353,76 @@ def run_beta_scan(args, desc):
     print(json.dumps(line), flush=True)
 
 
+def df_flops(n, naux):
+    """Flops of the density-fitted Eq. (Sigma) per tau point (gf2_sigma_tau_df)."""
+    return 4.0 * naux ** 2 * n ** 3 + 4.0 * naux ** 2 * n ** 2 + 8.0 * naux * n ** 3
+
+
+def run_sigma_df(args, sysm, desc):
+    """Density-fitted Eq. (Sigma) at every tau point of the workload, FP64 and FP32,
+    timed beside the dense contraction on the same G(tau) (the Hartree-Fock G(tau)
+    of iteration 0); one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1405_3273_amd import _lib as L
+    from paper_1405_3273_amd.runtime import Gf2
+
+    g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
+            ntau=sysm.ntau)
+    g.set_df_factors(sysm.B)
+    g.reset(mu0=float(np.mean(np.diag(sysm.h))))
+    g.iterate(L.make_params(prec="fp64"))
+    Gt = g.G_tau
+    naux, n, ntau = int(sysm.B.shape[0]), g.n, sysm.ntau
+    fl = df_flops(n, naux)
+    res = {}
+    for pr in [p for p in args.df_prec.split(",") if p]:
+        out = torch.empty_like(Gt)
+        g.sigma_tau_df(Gt[:4].contiguous(), pr)          # workspaces
+        torch.cuda.synchronize()
+        L.gf2_profile_enable(g.ctx, True)
+        t1 = time.perf_counter()
+        g.sigma_tau_df(Gt, pr, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        prof = L.gf2_profile_read(g.ctx)["sigma_df"]
+        L.gf2_profile_enable(g.ctx, False)
+        dense = torch.empty_like(Gt)
+        g.sigma_tau(Gt, pr, out=dense)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g.sigma_tau(Gt, pr, out=dense)
+        torch.cuda.synchronize()
+        dt_dense = time.perf_counter() - t2
+        diff = float((out - dense).abs().max() / dense.abs().max())
+        per_tau = prof[0] / prof[1] / 1e3
+        res[pr] = {"seconds": dt, "ms_per_tau": dt / ntau * 1e3,
+                   "tflops_algorithmic": fl * ntau / dt / 1e12,
+                   "event_ms_per_tau": per_tau * 1e3, "event_tflops": fl / per_tau / 1e12,
+                   "frac_of_peak": fl / per_tau / PEAK[pr],
+                   "dense_seconds": dt_dense, "dense_over_df_time": dt_dense / dt,
+                   "max_rel_diff_vs_dense": diff}
+        log(f"sigma_df {pr}: {dt:.2f} s ({dt / ntau * 1e3:.2f} ms per tau, "
+            f"{res[pr]['tflops_algorithmic']:.1f} TFLOP/s); dense {dt_dense * 1e3:.0f} ms; "
+            f"max rel diff {diff:.2e}")
+    g.close()
+    main_pr = [p for p in args.df_prec.split(",") if p][0]
+    r = res[main_pr]
+    line = {
+        "metric": "density-fitted Σ(τ) TFLOP/s (4 m²N³ + 4 m²N² + 8 mN³ per τ point)",
+        "value": r["tflops_algorithmic"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": r["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32"}[main_pr], "data": "synthetic",
+        "config": {"workload": desc, "mode": "density-fitted Sigma(tau), all tau points",
+                   "naux": naux, "n": n, "ntau": ntau, "G_tau": "Hartree-Fock G(tau) of iteration 0"},
+        "roofline": {"bound": "mfma", "achieved": r["event_tflops"], "peak": PEAK[main_pr] / 1e12,
+                     "unit": "TFLOP/s", "frac": r["frac_of_peak"], "traffic": None,
+                     "kernel": "sigma_df (one tau point: the whole GEMM chain)"},
+        "sigma_df": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +456,10 @@ def main():
     ap.add_argument("--tol-P-final", type=float, default=1e-10,
                     help="inner-loop max|dP| tolerance from the switch on (1e-10 before)")
     ap.add_argument("--max-outer", type=int, default=150)
+    ap.add_argument("--sigma-df", action="store_true",
+                    help="time the density-fitted Sigma(tau) (gf2_sigma_tau_df) at every tau\n"
+                         "point of the workload against the dense contraction; one JSON line")
+    ap.add_argument("--df-prec", default="fp64,fp32")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the workload (a kernel of known\n"
                          "traffic, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -424,6 +498,8 @@ def main():
         desc += f"; power tau grid {lv} x {per} ({sysm.ntau} points)"
     if args.converge:
         return run_converge(args, sysm, desc)
+    if args.sigma_df:
+        return run_sigma_df(args, sysm, desc)
     g = Gf2(sysm.S, sysm.h, sysm.v, nelec=sysm.nelec, beta=sysm.beta, niw=sysm.niw,
             ntau=sysm.ntau)
     if sysm.tau is not None:
@@ -458,7 +534,7 @@ def main():
             "sigma_s23": ("mfma", args.prec),
             "dyson": ("alu", "fp64_vector"), "t2i_expand": ("hbm", "hbm"),
             "i2t_fold": ("hbm", "hbm"), "fock": ("hbm", "hbm"),
-            "occupations": ("latency", None)}
+            "occupations": ("latency", None), "sigma_df": ("mfma", args.prec)}
     dom = max((k for k in prof if kind[k][0] != "latency"), key=lambda k: prof[k][0])
     ms, cnt, work = prof[dom]
     bound, pk = kind[dom]

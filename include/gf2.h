@@ -108,6 +108,10 @@ typedef struct {
                          /* |N - nelec| < max(tol_N, min(1e-6, tol_N_rel *      */
                          /* max|P_out - P_in| of pass k-1)); the inner loop     */
                          /* stops only after a pass that used tol_N.            */
+    int    sigma_df;     /* 0: Sigma(tau) from the integrals of gf2_set_system; */
+                         /* 1: from the density-fitting factors, as            */
+                         /* gf2_sigma_tau_df (prec FP64 or FP32; single-system */
+                         /* gf2_iterate only)                                  */
 } gf2_params;
 /* No outer-iteration limit and no determinism switch: gf2_iterate runs one
  * outer iteration, so the caller owns the outer loop, its limit and its stop
@@ -172,6 +176,40 @@ int gf2_set_system(gf2_ctx *ctx, int n, const double *S, const double *h, const 
  */
 int gf2_sigma_tau(gf2_ctx *ctx, const gf2_dims *dims, int prec,
                   const double *G_tau, double *Sigma_tau);
+
+/* gf2_set_df_factors: density-fitting factors of the integrals, the
+ * cheaper route to Eq. (Sigma) that the Implementation section proposes
+ * (recalled in the Conclusions): v_ijkl = sum_P B^P_ij B^P_kl over naux
+ * auxiliary functions P.  B: device [naux][n][n] FP64, each B^P symmetric
+ * (assumed, not checked), n that of gf2_set_system.  The factors are
+ * copied (with the layouts gf2_sigma_tau_df reads, FP64 and FP32); the
+ * context keeps them until the next gf2_set_df_factors or gf2_set_system,
+ * which drops them.  They are used only by gf2_sigma_tau_df and by
+ * gf2_iterate with prm->sigma_df = 1; v of gf2_set_system stays the
+ * integrals of the Fock build.
+ * Errors: GF2_EINVAL for naux < 1 or a NULL B; GF2_ESTATE without a system.
+ */
+int gf2_set_df_factors(gf2_ctx *ctx, int naux, const double *B);
+
+/* gf2_sigma_tau_df: Eq. (Sigma) with the factored integrals of
+ * gf2_set_df_factors.  With Y^P = B^P G(tau), X^PQ = Y^P B^Q and
+ * Gb = G(-tau), the two diagrams become
+ *   Sigma = -( 2 sum_PQ tr(X^PQ Gb) X^PQ - sum_PQ X^PQ Gb X^PQ ),
+ * evaluated on MFMA GEMMs in 4 naux^2 n^3 + 4 naux^2 n^2 + 8 naux n^3 flops
+ * per tau point: the direct term alone is O(naux n^3), the exchange term
+ * O(naux^2 n^3).  Arguments and output as gf2_sigma_tau (G_tau and Sigma_tau
+ * device [ntau][n][n] FP64, G symmetric, Sigma returned exactly symmetric);
+ * prec: GF2_PREC_FP64 (FP64 MFMA) or GF2_PREC_FP32 (FP32 MFMA and FP32
+ * intermediates, sums over more than 512 terms carried in FP64).
+ * Errors: GF2_ESTATE without factors; GF2_EINVAL for another prec, a
+ * dims->n that differs from the system, ntau < 4, aliasing, NULL pointers;
+ * GF2_ENOMEM if the workspace (4 naux n^2 + 2 n^2 + naux^2 elements, up to
+ * 1 GiB of exchange products and the split-K partial sums) cannot be
+ * allocated;
+ * GF2_ENONFINITE for a NaN or Inf in the result.
+ */
+int gf2_sigma_tau_df(gf2_ctx *ctx, const gf2_dims *dims, int prec,
+                     const double *G_tau, double *Sigma_tau);
 
 /* gf2_fourier: transforms between imaginary time and Matsubara frequency
  * (Implementation section: FFT with an analytic high-frequency tail).
@@ -339,6 +377,8 @@ int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
  *   GF2_KC_FOCK          Eq. (FockMatrix);                     work = bytes read (8 n^4)
  *   GF2_KC_OCCUPATIONS   natural occupation numbers (gf2_natural_occupations, all
  *                        three steps as one bracket);          work = n (eigenvalues)
+ *   GF2_KC_SIGMA_DF      density-fitted Eq. (Sigma), one bracket per tau point;
+ *                        work = flops (4 m^2 n^3 + 4 m^2 n^2 + 8 m n^3, m = naux)
  * gf2_profile_enable(ctx, 1) clears the counters and starts recording;
  * gf2_profile_enable(ctx, 0) stops.  gf2_profile_read synchronises the
  * stream and fills host arrays [nslots] (nslots <= GF2_KC_COUNT) with the
@@ -352,7 +392,8 @@ int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
 #define GF2_KC_FOCK         5
 #define GF2_KC_SIGMA_S23    6
 #define GF2_KC_OCCUPATIONS  7
-#define GF2_KC_COUNT        8
+#define GF2_KC_SIGMA_DF     8
+#define GF2_KC_COUNT        9
 
 int gf2_profile_enable(gf2_ctx *ctx, int on);
 int gf2_profile_read(gf2_ctx *ctx, int nslots, double *ms, long long *launches, double *work);

@@ -43,7 +43,8 @@ GF2_MU_SECANT = 2
 EXPORTED = ("gf2_ctx_create", "gf2_ctx_destroy", "gf2_last_error", "gf2_set_system",
             "gf2_sigma_tau", "gf2_fourier", "gf2_dyson", "gf2_fock", "gf2_density_fock",
             "gf2_iterate", "gf2_iterate_batched", "gf2_natural_occupations", "gf2_set_tau_grid",
-            "gf2_profile_enable", "gf2_profile_read", "gf2_dyson_noalloc")
+            "gf2_profile_enable", "gf2_profile_read", "gf2_dyson_noalloc",
+            "gf2_set_df_factors", "gf2_sigma_tau_df")
 
 GF2_KC_SIGMA_GEMM = 0
 GF2_KC_SIGMA_SPLITK = 1
@@ -53,9 +54,10 @@ GF2_KC_I2T_FOLD = 4
 GF2_KC_FOCK = 5
 GF2_KC_SIGMA_S23 = 6
 GF2_KC_OCCUPATIONS = 7
-GF2_KC_COUNT = 8
+GF2_KC_SIGMA_DF = 8
+GF2_KC_COUNT = 9
 KERNEL_CLASSES = ("sigma_gemm", "sigma_splitk", "dyson", "t2i_expand", "i2t_fold", "fock",
-                  "sigma_s23", "occupations")
+                  "sigma_s23", "occupations", "sigma_df")
 
 
 class Gf2Error(RuntimeError):
@@ -74,7 +76,7 @@ class gf2_params(C.Structure):
                 ("tol_E", C.c_double), ("max_inner", C.c_int), ("max_bisect", C.c_int),
                 ("mu_halfwidth", C.c_double), ("damp_P", C.c_double), ("mix_depth", C.c_int),
                 ("damp_Sigma", C.c_double), ("mu_method", C.c_int), ("prec", C.c_int),
-                ("tol_N_rel", C.c_double)]
+                ("tol_N_rel", C.c_double), ("sigma_df", C.c_int)]
 
 
 class gf2_state(C.Structure):
@@ -112,6 +114,8 @@ def load(path: str = None):
         "gf2_last_error": ([], C.c_char_p),
         "gf2_set_system": ([vp, i, vp, vp, vp], i),
         "gf2_sigma_tau": ([vp, C.POINTER(gf2_dims), i, vp, vp], i),
+        "gf2_set_df_factors": ([vp, i, vp], i),
+        "gf2_sigma_tau_df": ([vp, C.POINTER(gf2_dims), i, vp, vp], i),
         "gf2_fourier": ([vp, C.POINTER(gf2_dims), i, vp, vp, vp, vp], i),
         "gf2_dyson": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
         "gf2_dyson_noalloc": ([vp, C.POINTER(gf2_dims), i, d, vp, vp, vp, vp, vp, dp], i),
@@ -159,11 +163,11 @@ def make_dims(n, nelec, ntau, niw, beta) -> gf2_dims:
 
 def make_params(tol_mu=1e-12, tol_N=1e-10, tol_P=1e-10, tol_E=1e-11, max_inner=100,
                 max_bisect=200, mu_halfwidth=0.5, damp_P=0.3, mix_depth=8, damp_Sigma=0.0,
-                mu_method="secant", prec="fp32", tol_N_rel=0.0) -> gf2_params:
+                mu_method="secant", prec="fp32", tol_N_rel=0.0, sigma_df=False) -> gf2_params:
     mm = {"bisect": GF2_MU_BISECT, "illinois": GF2_MU_ILLINOIS, "secant": GF2_MU_SECANT}[mu_method]
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     return gf2_params(tol_mu, tol_N, tol_P, tol_E, max_inner, max_bisect, mu_halfwidth, damp_P,
-                      mix_depth, damp_Sigma, mm, pr, float(tol_N_rel))
+                      mix_depth, damp_Sigma, mm, pr, float(tol_N_rel), 1 if sigma_df else 0)
 
 
 # ---------------------------------------------------------------------------
@@ -193,6 +197,16 @@ def gf2_set_system(ctx, S, h, v):
 def gf2_sigma_tau(ctx, dims: gf2_dims, prec, G_tau, Sigma_tau):
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     _check(load().gf2_sigma_tau(ctx, C.byref(dims), pr, _ptr(G_tau), _ptr(Sigma_tau)))
+
+
+def gf2_set_df_factors(ctx, B):
+    """B: device [naux][n][n] FP64 density-fitting factors."""
+    _check(load().gf2_set_df_factors(ctx, int(B.shape[0]), _ptr(B)))
+
+
+def gf2_sigma_tau_df(ctx, dims: gf2_dims, prec, G_tau, Sigma_tau):
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(load().gf2_sigma_tau_df(ctx, C.byref(dims), pr, _ptr(G_tau), _ptr(Sigma_tau)))
 
 
 def gf2_fourier(ctx, dims: gf2_dims, direction, inp, moments, out, moment1_out=None):

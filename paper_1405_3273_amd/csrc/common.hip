@@ -330,7 +330,9 @@ int gf2_ctx_destroy(gf2_ctx *c) {
                            &c->grid_coef, &c->grid_plan, &c->it_Sig_iw, &c->it_G_iw, &c->it_Sig1,
                            &c->it_mom,   &c->it_Sig_new, &c->it_Pout, &c->it_Pin,  &c->it_F,
                            &c->it_tmp,   &c->it_hist,   &c->bat_tab,  &c->bat_boff,
-                           &c->bat_out,  &c->sig_tab,  &c->it_red,  &c->bat_red};
+                           &c->bat_out,  &c->sig_tab,  &c->it_red,  &c->bat_red,
+                           &c->df_B64,   &c->df_Bt64,   &c->df_B32,   &c->df_Bt32,
+                           &c->df_ws,    &c->df_T,      &c->df_part};
     for (auto *b : bufs) b->release();
     if (c->bat_red_h) (void)hipHostFree(c->bat_red_h);
     delete c;
@@ -344,6 +346,7 @@ int gf2_set_system(gf2_ctx *c, int n, const double *S, const double *h, const do
     GF2_HIP(hipSetDevice(c->device));
     const size_t n2 = (size_t)n * n, n4 = n2 * n2;
     c->has_system = false;
+    c->df_m = 0;
     c->have_f32_layouts = false;
     c->have_bf3_layouts = false;
     c->n = n;

@@ -584,7 +584,9 @@ static int check_params(const gf2_params *p, const char *who) {
         !(p->damp_P >= 0 && p->damp_P < 1) || !(p->damp_Sigma >= 0 && p->damp_Sigma < 1) ||
         (p->mu_method != GF2_MU_BISECT && p->mu_method != GF2_MU_ILLINOIS &&
          p->mu_method != GF2_MU_SECANT) ||
-        p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16MIX)
+        p->prec < GF2_PREC_FP64 || p->prec > GF2_PREC_BF16MIX ||
+        (p->sigma_df != 0 && p->sigma_df != 1) ||
+        (p->sigma_df == 1 && p->prec != GF2_PREC_FP64 && p->prec != GF2_PREC_FP32))
         return fail(GF2_EINVAL, std::string(who) + ": bad parameters");
     return GF2_OK;
 }
@@ -675,7 +677,10 @@ static int iter_sigma(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, gf2_st
     if (!need) return GF2_OK;
     GF2_HIP(hipStreamSynchronize(c->stream));
     const double ts = now_ms();
-    GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, c->it_Sig_new.as<double>()));
+    if (p->sigma_df)
+        GF2_TRY(sigma_df_run(c, d, p->prec, st->G_tau, c->it_Sig_new.as<double>()));
+    else
+        GF2_TRY(sigma_run(c, d, p->prec, st->G_tau, c->it_Sig_new.as<double>()));
     GF2_HIP(hipStreamSynchronize(c->stream));
     *t_sig += now_ms() - ts;
     return iter_sigma_post(c, d, p, st, Sig, Sig1, t_four);
@@ -730,6 +735,8 @@ extern "C" int gf2_iterate(gf2_ctx *c, const gf2_dims *d, const gf2_params *p, g
     GF2_TRY(check_dims(c, d, "gf2_iterate"));
     GF2_TRY(check_params(p, "gf2_iterate"));
     GF2_TRY(check_state(st, rep, "gf2_iterate"));
+    if (p->sigma_df && c->df_m < 1)
+        return fail(GF2_ESTATE, "gf2_iterate: sigma_df = 1 without density-fitting factors");
     GF2_HIP(hipSetDevice(c->device));
     const double t0 = now_ms();
     double t_sig = 0.0, t_four = 0.0;
@@ -775,6 +782,7 @@ extern "C" int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dim
     if (!ctxs || nsys < 1 || !dims || !states || !reps)
         return fail(GF2_EINVAL, "gf2_iterate_batched: NULL argument or nsys < 1");
     GF2_TRY(check_params(p, "gf2_iterate_batched"));
+    if (p->sigma_df) return fail(GF2_EINVAL, "gf2_iterate_batched: sigma_df is for gf2_iterate only");
     gf2_ctx *lead = ctxs[0];
     for (int s = 0; s < nsys; ++s) {
         GF2_TRY(check_dims(ctxs[s], &dims[s], "gf2_iterate_batched"));

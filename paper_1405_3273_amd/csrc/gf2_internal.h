@@ -125,6 +125,12 @@ struct gf2_ctx {
     void *sig_graph = nullptr;            // hipGraphExec_t of the batched Sigma
     long long sig_key = 0;
     long long bat_key = 0;                // shape the graph was captured for
+
+    // ---- density-fitting factors (gf2_set_df_factors) ----
+    int df_m = 0;                         // auxiliary functions (0: none set)
+    gf2::DevBuf df_B64, df_Bt64;          // B[P][a][b], Bt[a][P][b] (FP64)
+    gf2::DevBuf df_B32, df_Bt32;          // the same in FP32
+    gf2::DevBuf df_ws, df_T, df_part;     // chain intermediates, exchange products, split-K partials
 };
 
 namespace gf2 {
@@ -168,6 +174,8 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
                       int prec, const std::vector<const double *> &G,
                       const std::vector<double *> &Sig);
 void sigma_release(gf2_ctx *c);
+// density-fitted Sigma(tau) from the context's factors (prec FP64 or FP32)
+int sigma_df_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau);
 
 int fourier_tau2iw(gf2_ctx *c, const gf2_dims *d, const double *Sig_tau, double2 *Sig_iw,
                    double *Sig1);

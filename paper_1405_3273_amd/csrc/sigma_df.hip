@@ -1,0 +1,441 @@
+// Density-fitted form of Eq. (Sigma).
+//
+// The Implementation section proposes (and the Conclusions recall) factored
+// integrals as the cheaper route to the self-energy: v_ijkl = sum_P B^P_ij
+// B^P_kl over m auxiliary functions P.  Substituting the factors into both
+// integrals of Eq. (Sigma) and grouping the sums gives, with G = G(tau),
+// Gb = G(-tau), Y^P = B^P G and X^{PQ} = Y^P B^Q (all N x N),
+//
+//     Sigma = -( 2 sum_{PQ} tr(X^{PQ} Gb) X^{PQ} - sum_{PQ} X^{PQ} Gb X^{PQ} ),
+//
+// the direct and the exchange diagram.  For symmetric G, Gb and B^P the
+// device evaluates it as
+//
+//     Z^Q = B^Q Gb,   W^Q = Gb Y^Q,   Pi_PQ = sum_ac B^P_ac W^Q_ac  (= tr(X^{PQ} Gb)),
+//     U^P = sum_Q (Z^Q Y^P) B^Q - 2 sum_Q Pi_PQ B^Q,
+//     Sigma = sum_P Y^P U^P,
+//
+// since sum_PQ X^{PQ} Gb X^{PQ} = sum_P Y^P sum_Q (B^Q Gb Y^P) B^Q.  Flops per
+// tau point: 4 m^2 N^3 for the exchange products (Z^Q Y^P for every pair and
+// their contraction with B^Q), 4 m^2 N^2 for Pi and its contraction with B,
+// 8 m N^3 for Y, Z, W and the final product.  Only the direct term follows an
+// O(m N^3) count; the exchange term keeps the whole at O(m^2 N^3).
+//
+// Layouts (T = double or float, one tau point at a time):
+//   B[P][a][b], Bt[a][P][b] (= B^P_ab), Yt[i][P][b] (= Y^P_ib),
+//   Zt[a][Q][b] (= Z^Q_ab), W[Q][a][c], Pi[P][Q], U[P][b][j], and for a
+//   chunk of P the exchange products Tx[P][a][Q][c] = (Z^Q Y^P)_ac.
+// Every step is then a row-major GEMM with plain leading dimensions:
+//   Yt = Bt (mN x N) G,  Zt = Bt Gb,  W^Q = Gb Y^Q (batched over Q),
+//   Pi = B (m x N^2) W^T,  U = -2 Pi B,  Tx^P = Zt (mN x N) Y^P (batched over P),
+//   U += Tx (rows (P, a), K = (Q, c)) B (rows (Q, c)),  Sigma = Yt (N x mN) U.
+#include <algorithm>
+#include <cstdio>
+
+#include "gf2_internal.h"
+
+namespace gf2 {
+namespace {
+
+typedef double df_v4d __attribute__((ext_vector_type(4)));
+typedef float df_v4f __attribute__((ext_vector_type(4)));
+
+template <class T> struct DfAcc;
+template <> struct DfAcc<double> { typedef df_v4d type; };
+template <> struct DfAcc<float> { typedef df_v4f type; };
+
+// C(r, c) = alpha sum_k A(r, k) B(k, c) + beta C(r, c) for z = 0 .. batch-1:
+//   A(r, k) = A[z sA + r lda + k],
+//   B(k, c) = B[z sB + k ldb + c]   (or B[z sB + c ldb + k], the transposed form),
+//   C(r, c) = C[z sC + r ldc + c].
+// split = 1 (batch 1): z is a slice of kz along K and the kernel writes the
+// slice's sum to FP64 partials part[z][M][N]; k_df_reduce adds them in order.
+struct DfGemm {
+    const void *A;
+    long long lda, sA;
+    const void *B;
+    long long ldb, sB;
+    void *C;
+    long long ldc, sC;
+    int M, N, K;
+    int kz, split;
+    double alpha, beta;
+    double *part;
+};
+
+constexpr int DF_THREADS = 256;
+constexpr int DF_RT = 2;                  // 16-row tiles per wave
+constexpr int DF_BM = 64 * DF_RT;         // 4 waves stacked along rows
+constexpr int DF_BK = 16;
+constexpr int DF_FLUSH = 512 / DF_BK;     // FP32 form: chunks between FP64 flushes
+
+// Two workgroups per CU (two waves per SIMD: one loads and stores its next
+// chunk while the other runs MFMAs), except for the widest FP32 tile, whose
+// FP64 flush registers would then spill.
+template <class T, int NT> struct DfWaves {
+    static constexpr int value = (sizeof(T) == 8 || NT <= 7) ? 2 : 1;
+};
+
+template <class T, bool BT, int NT, class OutT>
+__global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm(DfGemm g) {
+    using acc_t = typename DfAcc<T>::type;
+    constexpr bool F64 = sizeof(T) == 8;
+    constexpr int BN = 16 * NT;
+    constexpr int SA = DF_BM + 16;                    // padded row strides
+    constexpr int SB = BN + ((16 - BN % 32) + 32) % 32;
+    __shared__ T As[DF_BK][SA];
+    __shared__ T Bs[DF_BK][SB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long r0 = (long long)blockIdx.x * DF_BM;
+    const int c0 = blockIdx.y * BN;
+    const int z = blockIdx.z;
+    const T *A = static_cast<const T *>(g.A);
+    const T *B = static_cast<const T *>(g.B);
+    int K = g.K;
+    if (g.split) {
+        const long long k0 = (long long)z * g.kz;
+        K = (int)std::min<long long>(g.kz, g.K - k0);
+        A += k0;
+        B += BT ? k0 : k0 * g.ldb;
+    } else {
+        A += (long long)z * g.sA;
+        B += (long long)z * g.sB;
+    }
+
+    acc_t acc[DF_RT][NT];
+    double accd[DF_RT][NT][4];
+#pragma unroll
+    for (int r = 0; r < DF_RT; ++r)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            acc[r][c] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) accd[r][c][e] = 0.0;
+        }
+
+    constexpr int A_PER = DF_BK * DF_BM / DF_THREADS;
+    constexpr int B_PER = (DF_BK * BN + DF_THREADS - 1) / DF_THREADS;
+    T ra[A_PER], rb[B_PER];
+    auto load = [&](int kb) {
+#pragma unroll
+        for (int e = 0; e < A_PER; ++e) {
+            const int idx = tid + e * DF_THREADS;
+            const long long gr = r0 + idx / DF_BK;
+            const int gk = kb + idx % DF_BK;
+            ra[e] = (gr < g.M && gk < K) ? A[gr * g.lda + gk] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < B_PER; ++e) {
+            const int idx = tid + e * DF_THREADS;
+            const int k = BT ? idx % DF_BK : idx / BN;
+            const int c = BT ? idx / DF_BK : idx % BN;
+            const int gk = kb + k, gc = c0 + c;
+            const bool ok = idx < DF_BK * BN && gk < K && gc < g.N;
+            rb[e] = ok ? (BT ? B[(long long)gc * g.ldb + gk] : B[(long long)gk * g.ldb + gc]) : T(0);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < A_PER; ++e) {
+            const int idx = tid + e * DF_THREADS;
+            As[idx % DF_BK][idx / DF_BK] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < B_PER; ++e) {
+            const int idx = tid + e * DF_THREADS;
+            if (idx < DF_BK * BN) {
+                if constexpr (BT) Bs[idx % DF_BK][idx / DF_BK] = rb[e];
+                else Bs[idx / BN][idx % BN] = rb[e];
+            }
+        }
+    };
+
+    const int nch = (K + DF_BK - 1) / DF_BK;
+    load(0);
+    for (int ch = 0; ch < nch; ++ch) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (ch + 1 < nch) load((ch + 1) * DF_BK);
+#pragma unroll
+        for (int k0 = 0; k0 < DF_BK; k0 += 4) {
+            const int kr = k0 + (lane >> 4);
+            T af[DF_RT], bf[NT];
+#pragma unroll
+            for (int r = 0; r < DF_RT; ++r) af[r] = As[kr][wave * (16 * DF_RT) + 16 * r + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) bf[c] = Bs[kr][16 * c + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < DF_RT; ++r)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    if constexpr (F64)
+                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[r][c], 0, 0, 0);
+                    else
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf[c], acc[r][c], 0, 0, 0);
+                }
+        }
+        if constexpr (!F64) {
+            if ((ch + 1) % DF_FLUSH == 0 || ch + 1 == nch) {
+#pragma unroll
+                for (int r = 0; r < DF_RT; ++r)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) accd[r][c][e] += (double)acc[r][c][e];
+                        acc[r][c] = acc_t{0, 0, 0, 0};
+                    }
+            }
+        }
+    }
+
+    // register e of a lane holds row lane/16 + 4e (FP64 MFMA) or 4 (lane/16) + e
+    // (FP32 MFMA), column lane % 16, of each 16 x 16 tile
+#pragma unroll
+    for (int r = 0; r < DF_RT; ++r)
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = F64 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+                const long long m = r0 + wave * (16 * DF_RT) + 16 * r + row;
+                const int n = c0 + 16 * c + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                const double val = F64 ? (double)acc[r][c][e] : accd[r][c][e];
+                if (g.split) {
+                    g.part[((long long)z * g.M + m) * g.N + n] = val;
+                } else {
+                    OutT *cp = static_cast<OutT *>(g.C) + (long long)z * g.sC + m * g.ldc + n;
+                    double o = g.alpha * val;
+                    if (g.beta != 0.0) o += g.beta * (double)*cp;
+                    *cp = (OutT)o;
+                }
+            }
+}
+
+// C(r, c) = alpha sum_z part[z][r][c] + beta C(r, c), slices added in order.
+template <class OutT>
+__global__ void k_df_reduce(int M, int N, int nz, const double *__restrict__ part, OutT *C,
+                            long long ldc, double alpha, double beta) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long MN = (long long)M * N;
+    if (idx >= MN) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[z * MN + idx];
+    OutT *cp = C + (idx / N) * ldc + idx % N;
+    double o = alpha * s;
+    if (beta != 0.0) o += beta * (double)*cp;
+    *cp = (OutT)o;
+}
+
+// B[P][a][b] (FP64) -> B and Bt[a][P][b] in T
+template <class T>
+__global__ void k_df_layouts(int n, int m, const double *__restrict__ B, T *__restrict__ Bf,
+                             T *__restrict__ Bt) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n2 = (long long)n * n;
+    if (idx >= n2 * m) return;
+    const long long P = idx / n2, ab = idx % n2, a = ab / n, b = ab % n;
+    const T x = (T)B[idx];
+    Bf[idx] = x;
+    Bt[(a * m + P) * n + b] = x;
+}
+
+// G = G(tau_k), Gb = G(-tau_k) = -G(tau_{M-k}) in T
+template <class T>
+__global__ void k_df_stage(int n2, const double *__restrict__ Gk, const double *__restrict__ Gmk,
+                           T *__restrict__ G, T *__restrict__ Gb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n2) return;
+    G[idx] = (T)Gk[idx];
+    Gb[idx] = (T)(-Gmk[idx]);
+}
+
+// Sigma_ij for j < i := Sigma_ji (the product is symmetric up to rounding;
+// the returned matrix is exactly symmetric, as the dense path's)
+__global__ void k_df_mirror(int n, double *S) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    const int i = idx / n, j = idx % n;
+    if (j < i) S[idx] = S[(long long)j * n + i];
+}
+
+// Column tiles per block: ceil(N/16) tiles in the fewest blocks of <= 8.
+void df_col_blocking(int N, int &nt, int &nblk) {
+    const int tiles = (N + 15) / 16;
+    nblk = (tiles + 7) / 8;
+    nt = (tiles + nblk - 1) / nblk;
+}
+
+template <class T, bool BT, class OutT>
+void df_launch(int nt, dim3 grid, hipStream_t s, const DfGemm &g) {
+    switch (nt) {
+#define GF2_DF_CASE(N_) \
+    case N_: hipLaunchKernelGGL((k_df_gemm<T, BT, N_, OutT>), grid, dim3(DF_THREADS), 0, s, g); break;
+        GF2_DF_CASE(1) GF2_DF_CASE(2) GF2_DF_CASE(3) GF2_DF_CASE(4)
+        GF2_DF_CASE(5) GF2_DF_CASE(6) GF2_DF_CASE(7) GF2_DF_CASE(8)
+#undef GF2_DF_CASE
+        default: break;
+    }
+}
+
+// Workgroups a launch should reach before K is split (a few per CU).
+constexpr long long DF_TARGET_WG = 1024;
+constexpr int DF_MIN_KSLICE = 256;
+
+// One GEMM (batch 1, possibly split along K) or a batch of them.
+template <class T, bool BT, class OutT>
+int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
+    int nt, nblk;
+    df_col_blocking(g.N, nt, nblk);
+    const long long rblk = (g.M + DF_BM - 1) / DF_BM;
+    const long long wg = rblk * nblk * batch;
+    if (rblk > 0x7fffffffLL || batch > 65535) return fail(GF2_EINVAL, "gf2_sigma_tau_df: problem too large");
+    int nz = batch;
+    g.split = 0;
+    g.kz = g.K;
+    if (batch == 1 && wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE) {
+        long long s = std::min<long long>((DF_TARGET_WG + wg - 1) / wg, g.K / DF_MIN_KSLICE);
+        const int kz = (int)(((g.K + s - 1) / s + DF_BK - 1) / DF_BK * DF_BK);
+        s = (g.K + kz - 1) / kz;
+        if (s > 1) {
+            GF2_TRY(c->df_part.ensure((size_t)s * g.M * g.N * sizeof(double)));
+            g.split = 1;
+            g.kz = kz;
+            g.part = c->df_part.as<double>();
+            nz = (int)s;
+        }
+    }
+    df_launch<T, BT, OutT>(nt, dim3((unsigned)rblk, (unsigned)nblk, (unsigned)nz), c->stream, g);
+    GF2_HIP(hipGetLastError());
+    if (g.split) {
+        const long long MN = (long long)g.M * g.N;
+        hipLaunchKernelGGL(k_df_reduce<OutT>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, c->stream,
+                           g.M, g.N, nz, (const double *)g.part, static_cast<OutT *>(g.C), g.ldc, g.alpha,
+                           g.beta);
+        GF2_HIP(hipGetLastError());
+    }
+    return GF2_OK;
+}
+
+DfGemm mk(const void *A, long long lda, const void *B, long long ldb, void *C, long long ldc, int M,
+          int N, int K, double alpha = 1.0, double beta = 0.0) {
+    DfGemm g{};
+    g.A = A; g.lda = lda;
+    g.B = B; g.ldb = ldb;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = alpha; g.beta = beta;
+    return g;
+}
+
+// Exchange products held at once: at most this many bytes (whole P slabs).
+constexpr size_t DF_T_BYTES = size_t(1) << 30;
+
+template <class T>
+int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau) {
+    const int N = c->n, m = c->df_m, ntau = d->ntau;
+    const long long N2 = (long long)N * N, mN = (long long)m * N, mN2 = mN * N;
+    const size_t slab = (size_t)mN2 * sizeof(T);      // Tx of one P
+    const int pc = (int)std::max<size_t>(1, std::min<size_t>(m, DF_T_BYTES / slab));
+    const size_t ws = (size_t)(2 * N2 + 4 * mN2 + (long long)m * m) * sizeof(T);
+    GF2_TRY(c->df_ws.ensure(ws));
+    GF2_TRY(c->df_T.ensure((size_t)pc * slab));
+    T *G = c->df_ws.as<T>(), *Gb = G + N2, *Yt = Gb + N2, *Zt = Yt + mN2, *W = Zt + mN2,
+      *U = W + mN2, *Pi = U + mN2;
+    T *Tx = c->df_T.as<T>();
+    const T *Bf = sizeof(T) == 8 ? (const T *)c->df_B64.ptr : (const T *)c->df_B32.ptr;
+    const T *Bt = sizeof(T) == 8 ? (const T *)c->df_Bt64.ptr : (const T *)c->df_Bt32.ptr;
+    const double flops = 4.0 * m * (double)m * N2 * N + 4.0 * m * (double)m * N2 + 8.0 * mN2 * N;
+
+    for (int k = 0; k < ntau; ++k) {
+        const int ph = c->prof ? prof_begin(c, GF2_KC_SIGMA_DF) : -1;
+        hipLaunchKernelGGL(k_df_stage<T>, dim3((unsigned)((N2 + 255) / 256)), dim3(256), 0, c->stream,
+                           (int)N2, G_tau + k * N2, G_tau + (long long)(ntau - 1 - k) * N2, G, Gb);
+        GF2_HIP(hipGetLastError());
+        // Yt = Bt G, Zt = Bt Gb
+        GF2_TRY((df_gemm<T, false, T>(c, mk(Bt, N, G, N, Yt, N, (int)mN, N, N), 1)));
+        GF2_TRY((df_gemm<T, false, T>(c, mk(Bt, N, Gb, N, Zt, N, (int)mN, N, N), 1)));
+        // W^Q = Gb Y^Q, Y^Q(b, c) = Yt[b][Q][c]
+        {
+            DfGemm g = mk(Gb, N, Yt, mN, W, N, N, N, N);
+            g.sA = 0; g.sB = N; g.sC = N2;
+            GF2_TRY((df_gemm<T, false, T>(c, g, m)));
+        }
+        // Pi_PQ = sum_k B[P][k] W[Q][k]
+        GF2_TRY((df_gemm<T, true, T>(c, mk(Bf, N2, W, N2, Pi, m, m, m, (int)N2), 1)));
+        // U = -2 Pi B
+        GF2_TRY((df_gemm<T, false, T>(c, mk(Pi, m, Bf, N2, U, N2, m, (int)N2, m, -2.0), 1)));
+        // exchange: Tx^P = Zt Y^P, then U[P0 ..] += Tx B
+        for (int P0 = 0; P0 < m; P0 += pc) {
+            const int np = std::min(pc, m - P0);
+            DfGemm g = mk(Zt, N, Yt + (long long)P0 * N, mN, Tx, N, (int)mN, N, N);
+            g.sA = 0; g.sB = N; g.sC = mN2;
+            GF2_TRY((df_gemm<T, false, T>(c, g, np)));
+            GF2_TRY((df_gemm<T, false, T>(c, mk(Tx, mN, Bf, N, U + (long long)P0 * N2, N, np * N, N,
+                                                  (int)mN, 1.0, 1.0), 1)));
+        }
+        // Sigma(tau_k) = Yt U (K = (P, b))
+        double *Sk = Sigma_tau + k * N2;
+        GF2_TRY((df_gemm<T, false, double>(c, mk(Yt, mN, U, N, Sk, N, N, N, (int)mN), 1)));
+        hipLaunchKernelGGL(k_df_mirror, dim3((unsigned)((N2 + 255) / 256)), dim3(256), 0, c->stream, N, Sk);
+        GF2_HIP(hipGetLastError());
+        if (c->prof) prof_end(c, ph, flops);
+    }
+    return GF2_OK;
+}
+
+}  // namespace
+
+int sigma_df_run(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau, double *Sigma_tau) {
+    if (c->df_m < 1) return fail(GF2_ESTATE, "Sigma(tau) from factors: no density-fitting factors set");
+    if (prec == GF2_PREC_FP64) return df_run<double>(c, d, G_tau, Sigma_tau);
+    if (prec == GF2_PREC_FP32) return df_run<float>(c, d, G_tau, Sigma_tau);
+    return fail(GF2_EINVAL, "Sigma(tau) from factors: prec must be GF2_PREC_FP64 or GF2_PREC_FP32");
+}
+
+}  // namespace gf2
+
+using namespace gf2;
+
+extern "C" int gf2_set_df_factors(gf2_ctx *c, int naux, const double *B) {
+    if (!c || !B) return fail(GF2_EINVAL, "gf2_set_df_factors: NULL argument");
+    if (naux < 1) return fail(GF2_EINVAL, "gf2_set_df_factors: naux must be >= 1");
+    if (!c->has_system) return fail(GF2_ESTATE, "gf2_set_df_factors: no system set");
+    GF2_HIP(hipSetDevice(c->device));
+    c->df_m = 0;
+    const size_t cnt = (size_t)naux * c->n * c->n;
+    GF2_TRY(c->df_B64.ensure(cnt * sizeof(double)));
+    GF2_TRY(c->df_Bt64.ensure(cnt * sizeof(double)));
+    GF2_TRY(c->df_B32.ensure(cnt * sizeof(float)));
+    GF2_TRY(c->df_Bt32.ensure(cnt * sizeof(float)));
+    const unsigned blocks = (unsigned)((cnt + 255) / 256);
+    hipLaunchKernelGGL(k_df_layouts<double>, dim3(blocks), dim3(256), 0, c->stream, c->n, naux, B,
+                       c->df_B64.as<double>(), c->df_Bt64.as<double>());
+    GF2_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_df_layouts<float>, dim3(blocks), dim3(256), 0, c->stream, c->n, naux, B,
+                       c->df_B32.as<float>(), c->df_Bt32.as<float>());
+    GF2_HIP(hipGetLastError());
+    c->df_m = naux;
+    return GF2_OK;
+}
+
+extern "C" int gf2_sigma_tau_df(gf2_ctx *c, const gf2_dims *d, int prec, const double *G_tau,
+                                double *Sigma_tau) {
+    if (!c || !d || !G_tau || !Sigma_tau) return fail(GF2_EINVAL, "gf2_sigma_tau_df: NULL argument");
+    if (!c->has_system) return fail(GF2_ESTATE, "gf2_sigma_tau_df: no system set");
+    if (c->df_m < 1) return fail(GF2_ESTATE, "gf2_sigma_tau_df: no density-fitting factors set");
+    if (d->n != c->n) return fail(GF2_EINVAL, "gf2_sigma_tau_df: dims->n differs from the system");
+    if (d->ntau < 4) return fail(GF2_EINVAL, "gf2_sigma_tau_df: ntau must be >= 4");
+    if (prec != GF2_PREC_FP64 && prec != GF2_PREC_FP32)
+        return fail(GF2_EINVAL, "gf2_sigma_tau_df: prec must be GF2_PREC_FP64 or GF2_PREC_FP32");
+    if ((const void *)G_tau == (const void *)Sigma_tau)
+        return fail(GF2_EINVAL, "gf2_sigma_tau_df: Sigma_tau aliases G_tau");
+    GF2_HIP(hipSetDevice(c->device));
+    GF2_TRY(sigma_df_run(c, d, prec, G_tau, Sigma_tau));
+    int bad = 0;
+    GF2_TRY(any_nonfinite(c, (size_t)d->ntau * d->n * d->n, Sigma_tau, &bad));
+    if (bad) return fail(GF2_ENONFINITE, "gf2_sigma_tau_df: non-finite self-energy");
+    return GF2_OK;
+}

@@ -57,6 +57,18 @@ class Gf2:
         L.gf2_sigma_tau(self.ctx, self.dims_with(ntau=ntau), prec, G_tau, out)
         return out
 
+    def set_df_factors(self, B):
+        """Density-fitting factors [naux][n][n] (v = sum_P B^P (x) B^P) for
+        sigma_tau_df and for iterations with params.sigma_df = 1."""
+        self.B = self.torch.as_tensor(B, dtype=self.torch.float64).to(self.device).contiguous()
+        L.gf2_set_df_factors(self.ctx, self.B)
+
+    def sigma_tau_df(self, G_tau, prec="fp64", out=None):
+        ntau = int(G_tau.shape[0])
+        out = self._empty(ntau, self.n, self.n) if out is None else out
+        L.gf2_sigma_tau_df(self.ctx, self.dims_with(ntau=ntau), prec, G_tau, out)
+        return out
+
     def tau_to_iw(self, Sig_tau, niw=None, beta=None):
         ntau = int(Sig_tau.shape[0])
         d = self.dims_with(ntau=ntau, niw=niw or self.dims.niw, beta=beta or self.dims.beta)
