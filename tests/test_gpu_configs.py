@@ -1,7 +1,9 @@
 """GPU runs of the remaining workload configurations at their full sizes:
 the lattice hopping scan (N = 32, FP64 against FP32 Sigma, one member against
-the oracle's stored iterations) and the N = 160 molecule-shaped system (one
-correlated FP32 iteration, Sigma(tau) sampled against the oracle)."""
+the oracle's stored iterations), the N = 160 molecule-shaped system (one
+correlated FP32 iteration, Sigma(tau) sampled against the oracle) and the
+N = 100 workload (the Sigma arithmetics' energies against FP64; the inexact mu
+search against the exact one)."""
 import json
 import os
 
@@ -113,3 +115,27 @@ def test_n100_split_forms_energy_against_fp64(torch):
         d = np.abs(np.array(energies[prec]) - np.array(energies["fp64"]))
         print(f"{prec} - fp64: {d}", flush=True)
         assert np.all(d <= bar), prec
+
+
+def test_n100_inexact_mu_search_reaches_the_same_iterations(torch):
+    """The benchmark's inexact mu search (tol_N_rel = 1e-2: early inner passes
+    locate mu loosely, every inner loop still ends on a pass that used tol_N)
+    against the loop as the oracle runs it (tol_N_rel = 0) on the N = 100
+    workload with FP32 Sigma: the Hartree-Fock iteration and four correlated
+    iterations agree to 1e-10 relative in the energy and 1e-9 in mu, with fewer
+    Dyson evaluations."""
+    from paper_1405_3273_amd import make_params
+    from synthetic import molecule_n100
+    s = molecule_n100()
+    runs = {}
+    for rel in (0.0, 1e-2):
+        g = _make(s)
+        prm = make_params(damp_Sigma=0.5, prec="fp32", tol_N_rel=rel)
+        runs[rel] = [g.iterate(prm) for _ in range(5)]
+        print(f"tol_N_rel {rel}: " + " ".join(f"{r.energy:.12f}/{r.n_eval}" for r in runs[rel]),
+              flush=True)
+        g.close()
+    for a, b in zip(runs[0.0], runs[1e-2]):
+        assert b.energy == pytest.approx(a.energy, rel=1e-10)
+        assert b.mu == pytest.approx(a.mu, abs=1e-9)
+    assert sum(r.n_eval for r in runs[1e-2]) < sum(r.n_eval for r in runs[0.0])
