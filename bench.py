@@ -52,7 +52,7 @@ def sigma_flops(n, ntau):
 
 KERNEL_SOURCES = {"dyson": "dyson.hip", "sigma_gemm": "sigma.hip", "sigma_s23": "sigma.hip",
                   "sigma_splitk": "sigma.hip", "t2i_expand": "fourier.hip", "i2t_fold": "fourier.hip",
-                  "fock": "fock.hip"}
+                  "fock": "fock.hip", "sigma_df": "sigma_df.hip"}
 
 
 def source_hash(kernel_class):
@@ -416,7 +416,8 @@ def run_sigma_df(args, sysm, desc):
         "config": {"workload": desc, "mode": "density-fitted Sigma(tau), all tau points",
                    "naux": naux, "n": n, "ntau": ntau, "G_tau": "Hartree-Fock G(tau) of iteration 0"},
         "roofline": {"bound": "mfma", "achieved": r["event_tflops"], "peak": PEAK[main_pr] / 1e12,
-                     "unit": "TFLOP/s", "frac": r["frac_of_peak"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": r["frac_of_peak"],
+                     "traffic": measured_traffic("sigma_df", args.workload, main_pr),
                      "kernel": "sigma_df (one tau point: the whole GEMM chain)"},
         "sigma_df": res,
     }
