@@ -1926,13 +1926,16 @@ static int build_bf3_layouts(gf2_ctx *c) {
 
 // ---------------------------------------------------------------------------
 // One system's Sigma(tau): sizes, workspaces and launch shapes.  The tau batch
-// b and the waves per S23 workgroup change only which workgroup computes
-// which independent result, never the arithmetic of a result, so the
-// autotuner below may pick them freely.
+// b, the waves per S23 workgroup and the tile shapes change only which
+// workgroup computes which independent result, never the arithmetic of a result
+// (the first transform's K chunks are added in the same k order whatever their
+// depth), so the autotuner below may pick them freely.
 struct SigShape {
     int b = 0;
     int waves = 0;
-    int s4cb = 0;   // FP64/FP32 final contraction: column blocks per row block (1 or 2)
+    int s4cb = 0;    // FP64/FP32 final contraction: column blocks per row block (1 or 2)
+    int s1_bk = 0;   // first transform, FP32 kernel: K chunk (16 or 20; 0 = by n)
+    int s1_nt = 0;   // first transform: 16-column tiles per workgroup (0 = fewest blocks of <= 8)
 };
 
 struct SigPlan {
@@ -1940,7 +1943,7 @@ struct SigPlan {
     int mode = 0, n = 0, ntau = 0, M = 0;
     const double *G = nullptr;
     double *Sig = nullptr;
-    int KT = 0, SL = 0, lq = 0, KP = 0, SLG = 0, nsplit = 0, s1_bk = 16;
+    int KT = 0, SL = 0, lq = 0, KP = 0, SLG = 0, nsplit = 0, s1_bk = 16, s1_nt = 0;
     int s4_nt = 0;   // 16-column tiles per S4 workgroup (KT split over sh.s4cb blocks)
     long long kz = 0;
     size_t t1_plane = 0, gq_plane = 0;
@@ -1986,6 +1989,8 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
     if (N3 < 8 * 4096) p.kz = std::max<long long>(512, ((N3 / 8) + 511) / 512 * 512);
     p.nsplit = (int)((N3 + p.kz - 1) / p.kz);
     p.s1_bk = (s1_mode(p.mode) == MODE_F32 && n % 16 != 0 && n % 20 == 0) ? 20 : 16;
+    if (s1_mode(p.mode) == MODE_F32 && (sh.s1_bk == 16 || sh.s1_bk == 20)) p.s1_bk = sh.s1_bk;
+    p.s1_nt = (sh.s1_nt >= 1 && sh.s1_nt <= 8) ? sh.s1_nt : 0;
     const int bmax = sigma_bmax(n, p.mode);
     p.sh.b = std::max(1, std::min(sh.b > 0 ? sh.b : bmax, std::min(bmax, ntau)));
     const int wmax = (p.mode == MODE_F64) ? max_waves<MODE_F64>(p.KT)
@@ -2075,7 +2080,11 @@ static GemmArgs plan_s1(const SigPlan &p, int nb, int &nt) {
         g.sC = R * N * p.lq;
         g.plane = (long long)p.t1_plane;
     }
-    const dim3 grid = gemm_grid(g, p.n, nt);
+    dim3 grid = gemm_grid(g, p.n, nt);
+    if (p.s1_nt > 0) {   // tuned column tile
+        nt = p.s1_nt;
+        grid.y = (unsigned)(((g.N + 15) / 16 + nt - 1) / nt);
+    }
     g.gx = (int)grid.x;
     g.gy = (int)grid.y;
     g.gz = (int)grid.z;
@@ -2223,13 +2232,13 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, SigShape> g_tune;
 
 static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape &out) {
-    // GF2_SIGMA_SHAPE="b,waves[,s4cb]" forces a shape (read on every call; for tests
-    // of the invariance and for sweeps)
+    // GF2_SIGMA_SHAPE="b,waves[,s4cb[,s1_bk,s1_nt]]" forces a shape (read on every
+    // call; for tests of the invariance and for sweeps)
     if (const char *fs = std::getenv("GF2_SIGMA_SHAPE")) {
-        int b = 0, w = 0, cb = 0;
-        const int got = std::sscanf(fs, "%d,%d,%d", &b, &w, &cb);
+        int b = 0, w = 0, cb = 0, bk = 0, nt = 0;
+        const int got = std::sscanf(fs, "%d,%d,%d,%d,%d", &b, &w, &cb, &bk, &nt);
         if (got >= 2 && b > 0 && w > 0) {
-            out = SigShape{b, w, got == 3 ? cb : 0};
+            out = SigShape{b, w, got >= 3 ? cb : 0, got >= 5 ? bk : 0, got >= 5 ? nt : 0};
             return GF2_OK;
         }
     }
@@ -2282,6 +2291,40 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
             if (rc != GF2_OK) break;
           }
           if (rc != GF2_OK) break;
+        }
+        // the first transform's tile shape, timed alone on the best tau batch
+        // (its output, and so the later stages, do not depend on it)
+        if (rc == GF2_OK) {
+            std::vector<std::pair<int, int>> s1c{{0, 0}, {16, 4}, {16, 8}};
+            if (s1_mode(prec) == MODE_F32 && c->n % 20 == 0) s1c.push_back({20, 4});
+            double best_s1 = 1e300;
+            for (auto bn : s1c) {
+                SigShape sh = best;
+                sh.s1_bk = bn.first;
+                sh.s1_nt = bn.second;
+                SigPlan p;
+                rc = plan_init(c, ntau, prec, G, Sig, sh, p);
+                if (rc != GF2_OK) break;
+                const int nb = std::min(p.sh.b, ntau);
+                rc = plan_stage(p, c->stream, 0, nb);
+                if (rc != GF2_OK) break;
+                int nt;
+                KRef<GemmArgs> r{};
+                r.one = plan_s1(p, nb, nt);
+                const dim3 grid(xcd_grid((long long)r.one.gx * r.one.gy * r.one.gz));
+                (void)hipEventRecord(e0, c->stream);
+                rc = launch_s1(p.mode, p.s1_bk, nt, grid, c->stream, r);
+                (void)hipEventRecord(e1, c->stream);
+                if (rc != GF2_OK) break;
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(GF2_EHIP, "autotuner: event"); break; }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_s1) {
+                    best_s1 = ms;
+                    best.s1_bk = bn.first;
+                    best.s1_nt = bn.second;
+                }
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2347,7 +2390,7 @@ int sigma_run_batched(gf2_ctx *lead, const std::vector<gf2_ctx *> &cs, const std
     long long key = 1469598103934665603LL ^ prec;
     auto mix = [&](long long v) { key = (key ^ v) * 1099511628211LL; };
     for (auto &p : plans) {
-        mix(p.n); mix(p.ntau); mix(p.sh.b); mix(p.sh.waves); mix(p.sh.s4cb);
+        mix(p.n); mix(p.ntau); mix(p.sh.b); mix(p.sh.waves); mix(p.sh.s4cb); mix(p.s1_bk); mix(p.s1_nt);
         mix((long long)(uintptr_t)p.G); mix((long long)(uintptr_t)p.Sig);
         mix((long long)(uintptr_t)p.c->sig_T1.ptr); mix((long long)(uintptr_t)p.c->sig_X.ptr);
         mix((long long)(uintptr_t)p.c->sig_part.ptr); mix((long long)(uintptr_t)p.c->sig_Gp.ptr);

@@ -281,8 +281,9 @@ def test_density_fock_rejects_impossible_electron_count(torch):
 @pytest.mark.parametrize("n", [17, 40])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6", "bf16mix"])
 def test_sigma_shape_invariant(torch, n, prec):
-    """The tuned launch shape (tau batch, waves per S23 workgroup) moves work
-    between workgroups only: every shape gives bitwise the same Sigma(tau)."""
+    """The tuned launch shape (tau batch, waves per S23 workgroup, final
+    contraction column blocks, first transform K chunk and column tile) moves
+    work between workgroups only: every shape gives bitwise the same Sigma(tau)."""
     import os
     print(f"sigma shapes n={n} prec={prec}", flush=True)
     ntau = 11
@@ -291,8 +292,8 @@ def test_sigma_shape_invariant(torch, n, prec):
     g = _gf2(s)
     outs = []
     try:
-        for b, w in [(11, 4), (4, 8), (1, 16), (3, 4)]:
-            os.environ["GF2_SIGMA_SHAPE"] = f"{b},{w}"
+        for shape in ["11,4", "4,8", "1,16", "3,4", "11,8,2,16,3", "4,4,1,20,1", "3,8,1,16,8"]:
+            os.environ["GF2_SIGMA_SHAPE"] = shape
             outs.append(g.sigma_tau(Gt, prec).cpu().numpy())
     finally:
         os.environ.pop("GF2_SIGMA_SHAPE", None)
