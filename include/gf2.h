@@ -195,17 +195,20 @@ int gf2_set_df_factors(gf2_ctx *ctx, int naux, const double *B);
  * gf2_set_df_factors.  With Y^P = B^P G(tau), X^PQ = Y^P B^Q and
  * Gb = G(-tau), the two diagrams become
  *   Sigma = -( 2 sum_PQ tr(X^PQ Gb) X^PQ - sum_PQ X^PQ Gb X^PQ ),
- * evaluated on MFMA GEMMs in 4 naux^2 n^3 + 4 naux^2 n^2 + 8 naux n^3 flops
- * per tau point: the direct term alone is O(naux n^3), the exchange term
- * O(naux^2 n^3).  Arguments and output as gf2_sigma_tau (G_tau and Sigma_tau
+ * evaluated on MFMA GEMMs.  The direct term costs O(naux n^3 + naux^2 n^2)
+ * flops per tau point; the exchange term is taken either as the products of
+ * every factor pair (4 naux^2 n^3 flops) or through the n^4 tensor
+ * sum_Q (B^Q Gb) (x) B^Q (4 naux n^4 flops), the latter when naux > n and
+ * its two n^4 arrays fit in 16 GiB (GF2_DF_ROUTE=pair|tensor in the
+ * environment forces one).  Arguments and output as gf2_sigma_tau (G_tau and Sigma_tau
  * device [ntau][n][n] FP64, G symmetric, Sigma returned exactly symmetric);
  * prec: GF2_PREC_FP64 (FP64 MFMA) or GF2_PREC_FP32 (FP32 MFMA and FP32
  * intermediates, sums over more than 512 terms carried in FP64).
  * Errors: GF2_ESTATE without factors; GF2_EINVAL for another prec, a
  * dims->n that differs from the system, ntau < 4, aliasing, NULL pointers;
- * GF2_ENOMEM if the workspace (4 naux n^2 + 2 n^2 + naux^2 elements, up to
- * 1 GiB of exchange products and the split-K partial sums) cannot be
- * allocated;
+ * GF2_ENOMEM if the workspace (5 naux n^2 + 2 n^2 + naux^2 elements, the
+ * split-K partial sums, and 1 GiB of pair products or the two n^4 arrays)
+ * cannot be allocated;
  * GF2_ENONFINITE for a NaN or Inf in the result.
  */
 int gf2_sigma_tau_df(gf2_ctx *ctx, const gf2_dims *dims, int prec,
@@ -378,7 +381,9 @@ int gf2_iterate_batched(gf2_ctx *const *ctxs, int nsys, const gf2_dims *dims,
  *   GF2_KC_OCCUPATIONS   natural occupation numbers (gf2_natural_occupations, all
  *                        three steps as one bracket);          work = n (eigenvalues)
  *   GF2_KC_SIGMA_DF      density-fitted Eq. (Sigma), one bracket per tau point;
- *                        work = flops (4 m^2 n^3 + 4 m^2 n^2 + 8 m n^3, m = naux)
+ *                        work = flops of the route taken (m = naux): pair route
+ *                        4 m^2 n^3 + 4 m^2 n^2 + 8 m n^3, tensor route
+ *                        4 m n^4 + 4 m^2 n^2 + 10 m n^3
  * gf2_profile_enable(ctx, 1) clears the counters and starts recording;
  * gf2_profile_enable(ctx, 0) stops.  gf2_profile_read synchronises the
  * stream and fills host arrays [nslots] (nslots <= GF2_KC_COUNT) with the

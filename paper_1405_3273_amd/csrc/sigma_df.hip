@@ -15,17 +15,17 @@
 //     U^P = sum_Q (Z^Q Y^P) B^Q - 2 sum_Q Pi_PQ B^Q,
 //     Sigma = sum_P Y^P U^P,
 //
-// since sum_PQ X^{PQ} Gb X^{PQ} = sum_P Y^P sum_Q (B^Q Gb Y^P) B^Q.  Flops per
-// tau point: 4 m^2 N^3 for the exchange products (Z^Q Y^P for every pair and
-// their contraction with B^Q), 4 m^2 N^2 for Pi and its contraction with B,
-// 8 m N^3 for Y, Z, W and the final product.  Only the direct term follows an
-// O(m N^3) count; the exchange term keeps the whole at O(m^2 N^3).
+// since sum_PQ X^{PQ} Gb X^{PQ} = sum_P Y^P sum_Q (B^Q Gb Y^P) B^Q.  The direct
+// term costs 4 m^2 N^2 + 6 m N^3 flops (Pi, its contraction with B, Y, W and the
+// final product): the O(m N^3) the method's estimate names.  The exchange term
+// needs every pair (P, Q): 4 m^2 N^3 flops as pair products, or 4 m N^4 through
+// the N^4 tensor sum_Q Z^Q (x) B^Q (see df_run); neither is O(m N^3).
 //
 // Layouts (T = double or float, one tau point at a time):
 //   B[P][a][b], Bt[a][P][b] (= B^P_ab), Yt[i][P][b] (= Y^P_ib),
 //   Zt[a][Q][b] (= Z^Q_ab), W[Q][a][c], Pi[P][Q], U[P][b][j], and for a
 //   chunk of P the exchange products Tx[P][a][Q][c] = (Z^Q Y^P)_ac.
-// Every step is then a row-major GEMM with plain leading dimensions:
+// Every step is then a GEMM with plain leading dimensions:
 //   Yt = Bt (mN x N) G,  Zt = Bt Gb,  W^Q = Gb Y^Q (batched over Q),
 //   Pi = B (m x N^2) W^T,  U = -2 Pi B,  Tx^P = Zt (mN x N) Y^P (batched over P),
 //   U += Tx (rows (P, a), K = (Q, c)) B (rows (Q, c)),  Sigma = Yt (N x mN) U.
@@ -45,7 +45,7 @@ template <> struct DfAcc<double> { typedef df_v4d type; };
 template <> struct DfAcc<float> { typedef df_v4f type; };
 
 // C(r, c) = alpha sum_k A(r, k) B(k, c) + beta C(r, c) for z = 0 .. batch-1:
-//   A(r, k) = A[z sA + r lda + k],
+//   A(r, k) = A[z sA + r lda + k]   (or A[z sA + k lda + r], the transposed form),
 //   B(k, c) = B[z sB + k ldb + c]   (or B[z sB + c ldb + k], the transposed form),
 //   C(r, c) = C[z sC + r ldc + c].
 // split = 1 (batch 1): z is a slice of kz along K and the kernel writes the
@@ -76,7 +76,7 @@ template <class T, int NT> struct DfWaves {
     static constexpr int value = (sizeof(T) == 8 || NT <= 7) ? 2 : 1;
 };
 
-template <class T, bool BT, int NT, class OutT>
+template <class T, bool AT, bool BT, int NT, class OutT>
 __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm(DfGemm g) {
     using acc_t = typename DfAcc<T>::type;
     constexpr bool F64 = sizeof(T) == 8;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
     if (g.split) {
         const long long k0 = (long long)z * g.kz;
         K = (int)std::min<long long>(g.kz, g.K - k0);
-        A += k0;
+        A += AT ? k0 * g.lda : k0;
         B += BT ? k0 : k0 * g.ldb;
     } else {
         A += (long long)z * g.sA;
@@ -121,9 +121,9 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
 #pragma unroll
         for (int e = 0; e < A_PER; ++e) {
             const int idx = tid + e * DF_THREADS;
-            const long long gr = r0 + idx / DF_BK;
-            const int gk = kb + idx % DF_BK;
-            ra[e] = (gr < g.M && gk < K) ? A[gr * g.lda + gk] : T(0);
+            const long long gr = r0 + (AT ? idx % DF_BM : idx / DF_BK);
+            const int gk = kb + (AT ? idx / DF_BM : idx % DF_BK);
+            ra[e] = (gr < g.M && gk < K) ? (AT ? A[(long long)gk * g.lda + gr] : A[gr * g.lda + gk]) : T(0);
         }
 #pragma unroll
         for (int e = 0; e < B_PER; ++e) {
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
 #pragma unroll
         for (int e = 0; e < A_PER; ++e) {
             const int idx = tid + e * DF_THREADS;
-            As[idx % DF_BK][idx / DF_BK] = ra[e];
+            if constexpr (AT) As[idx / DF_BM][idx % DF_BM] = ra[e];
+            else As[idx % DF_BK][idx / DF_BK] = ra[e];
         }
 #pragma unroll
         for (int e = 0; e < B_PER; ++e) {
@@ -261,6 +262,17 @@ __global__ void k_df_mirror(int n, double *S) {
     if (j < i) S[idx] = S[(long long)j * n + i];
 }
 
+// Vp[b][c][a][j] = V[a][b][c][j] (the exchange tensor regrouped so that the
+// last product contracts (b, c) as one row index)
+template <class T>
+__global__ void k_df_permute(int n, const T *__restrict__ V, T *__restrict__ Vp) {
+    const long long n2 = (long long)n * n;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n2 * n2) return;
+    const long long j = idx % n, t1 = idx / n, a = t1 % n, t2 = t1 / n, c = t2 % n, b = t2 / n;
+    Vp[idx] = V[((a * n + b) * n + c) * n + j];
+}
+
 // Column tiles per block: ceil(N/16) tiles in the fewest blocks of <= 8.
 void df_col_blocking(int N, int &nt, int &nblk) {
     const int tiles = (N + 15) / 16;
@@ -268,11 +280,11 @@ void df_col_blocking(int N, int &nt, int &nblk) {
     nt = (tiles + nblk - 1) / nblk;
 }
 
-template <class T, bool BT, class OutT>
+template <class T, bool AT, bool BT, class OutT>
 void df_launch(int nt, dim3 grid, hipStream_t s, const DfGemm &g) {
     switch (nt) {
 #define GF2_DF_CASE(N_) \
-    case N_: hipLaunchKernelGGL((k_df_gemm<T, BT, N_, OutT>), grid, dim3(DF_THREADS), 0, s, g); break;
+    case N_: hipLaunchKernelGGL((k_df_gemm<T, AT, BT, N_, OutT>), grid, dim3(DF_THREADS), 0, s, g); break;
         GF2_DF_CASE(1) GF2_DF_CASE(2) GF2_DF_CASE(3) GF2_DF_CASE(4)
         GF2_DF_CASE(5) GF2_DF_CASE(6) GF2_DF_CASE(7) GF2_DF_CASE(8)
 #undef GF2_DF_CASE
@@ -285,7 +297,7 @@ constexpr long long DF_TARGET_WG = 1024;
 constexpr int DF_MIN_KSLICE = 256;
 
 // One GEMM (batch 1, possibly split along K) or a batch of them.
-template <class T, bool BT, class OutT>
+template <class T, bool AT, bool BT, class OutT>
 int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
     int nt, nblk;
     df_col_blocking(g.N, nt, nblk);
@@ -307,7 +319,7 @@ int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
             nz = (int)s;
         }
     }
-    df_launch<T, BT, OutT>(nt, dim3((unsigned)rblk, (unsigned)nblk, (unsigned)nz), c->stream, g);
+    df_launch<T, AT, BT, OutT>(nt, dim3((unsigned)rblk, (unsigned)nblk, (unsigned)nz), c->stream, g);
     GF2_HIP(hipGetLastError());
     if (g.split) {
         const long long MN = (long long)g.M * g.N;
@@ -332,53 +344,86 @@ DfGemm mk(const void *A, long long lda, const void *B, long long ldb, void *C, l
 
 // Exchange products held at once: at most this many bytes (whole P slabs).
 constexpr size_t DF_T_BYTES = size_t(1) << 30;
+// The tensor route's two N^4 arrays may take at most this many bytes.
+constexpr size_t DF_V_BYTES = size_t(16) << 30;
 
+// Two evaluations of the exchange term, equal up to rounding:
+//   pair route:   U^P += sum_Q (Z^Q Y^P) B^Q, the products of every (P, Q) pair in
+//                 chunks of P: 4 m^2 N^3 flops, O(m N^2) memory besides a 1 GiB chunk;
+//   tensor route: V[(a,b)][(c,j)] = sum_Q Z^Q_ab B^Q_cj once (one GEMM over Q), then
+//                 U^P_aj += sum_{b,c} Y^P_bc V[(a,b)][(c,j)] for all P (one GEMM over
+//                 (b, c)): 4 m N^4 flops and two N^4 arrays.
+// The tensor route needs fewer flops when m > N (every configuration here), the pair
+// route less memory; the tensor route is taken when m > N and its arrays fit in
+// DF_V_BYTES.  GF2_DF_ROUTE=pair|tensor in the environment forces one (tests).
 template <class T>
 int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau) {
     const int N = c->n, m = c->df_m, ntau = d->ntau;
-    const long long N2 = (long long)N * N, mN = (long long)m * N, mN2 = mN * N;
-    const size_t slab = (size_t)mN2 * sizeof(T);      // Tx of one P
+    const long long N2 = (long long)N * N, N4 = N2 * N2, mN = (long long)m * N, mN2 = mN * N;
+    bool tensor = m > N && (size_t)(2 * N4) * sizeof(T) <= DF_V_BYTES;
+    if (const char *e = std::getenv("GF2_DF_ROUTE")) {
+        if (e[0] == 'p') tensor = false;
+        if (e[0] == 't') tensor = true;
+    }
+    const size_t slab = (size_t)mN2 * sizeof(T);      // Tx of one P (pair route)
     const int pc = (int)std::max<size_t>(1, std::min<size_t>(m, DF_T_BYTES / slab));
-    const size_t ws = (size_t)(2 * N2 + 4 * mN2 + (long long)m * m) * sizeof(T);
+    const size_t ws = (size_t)(2 * N2 + 5 * mN2 + (long long)m * m) * sizeof(T);
     GF2_TRY(c->df_ws.ensure(ws));
-    GF2_TRY(c->df_T.ensure((size_t)pc * slab));
+    GF2_TRY(c->df_T.ensure(tensor ? (size_t)(2 * N4) * sizeof(T) : (size_t)pc * slab));
     T *G = c->df_ws.as<T>(), *Gb = G + N2, *Yt = Gb + N2, *Zt = Yt + mN2, *W = Zt + mN2,
-      *U = W + mN2, *Pi = U + mN2;
+      *U = W + mN2, *Y = U + mN2, *Pi = Y + mN2;
     T *Tx = c->df_T.as<T>();
+    T *V = Tx, *Vp = Tx + N4;                        // tensor route
+    T *Z = Zt;                                       // tensor route: Z[Q][a][b] in Zt's space
     const T *Bf = sizeof(T) == 8 ? (const T *)c->df_B64.ptr : (const T *)c->df_B32.ptr;
     const T *Bt = sizeof(T) == 8 ? (const T *)c->df_Bt64.ptr : (const T *)c->df_Bt32.ptr;
-    const double flops = 4.0 * m * (double)m * N2 * N + 4.0 * m * (double)m * N2 + 8.0 * mN2 * N;
+    const double flops = tensor ? 4.0 * m * (double)N4 + 10.0 * mN2 * N + 4.0 * m * (double)m * N2
+                                : 4.0 * m * (double)m * N2 * N + 4.0 * m * (double)m * N2 + 8.0 * mN2 * N;
 
     for (int k = 0; k < ntau; ++k) {
         const int ph = c->prof ? prof_begin(c, GF2_KC_SIGMA_DF) : -1;
         hipLaunchKernelGGL(k_df_stage<T>, dim3((unsigned)((N2 + 255) / 256)), dim3(256), 0, c->stream,
                            (int)N2, G_tau + k * N2, G_tau + (long long)(ntau - 1 - k) * N2, G, Gb);
         GF2_HIP(hipGetLastError());
-        // Yt = Bt G, Zt = Bt Gb
-        GF2_TRY((df_gemm<T, false, T>(c, mk(Bt, N, G, N, Yt, N, (int)mN, N, N), 1)));
-        GF2_TRY((df_gemm<T, false, T>(c, mk(Bt, N, Gb, N, Zt, N, (int)mN, N, N), 1)));
+        // Yt = Bt G (rows (i, P))
+        GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bt, N, G, N, Yt, N, (int)mN, N, N), 1)));
         // W^Q = Gb Y^Q, Y^Q(b, c) = Yt[b][Q][c]
         {
             DfGemm g = mk(Gb, N, Yt, mN, W, N, N, N, N);
             g.sA = 0; g.sB = N; g.sC = N2;
-            GF2_TRY((df_gemm<T, false, T>(c, g, m)));
+            GF2_TRY((df_gemm<T, false, false, T>(c, g, m)));
         }
         // Pi_PQ = sum_k B[P][k] W[Q][k]
-        GF2_TRY((df_gemm<T, true, T>(c, mk(Bf, N2, W, N2, Pi, m, m, m, (int)N2), 1)));
+        GF2_TRY((df_gemm<T, false, true, T>(c, mk(Bf, N2, W, N2, Pi, m, m, m, (int)N2), 1)));
         // U = -2 Pi B
-        GF2_TRY((df_gemm<T, false, T>(c, mk(Pi, m, Bf, N2, U, N2, m, (int)N2, m, -2.0), 1)));
-        // exchange: Tx^P = Zt Y^P, then U[P0 ..] += Tx B
-        for (int P0 = 0; P0 < m; P0 += pc) {
-            const int np = std::min(pc, m - P0);
-            DfGemm g = mk(Zt, N, Yt + (long long)P0 * N, mN, Tx, N, (int)mN, N, N);
-            g.sA = 0; g.sB = N; g.sC = mN2;
-            GF2_TRY((df_gemm<T, false, T>(c, g, np)));
-            GF2_TRY((df_gemm<T, false, T>(c, mk(Tx, mN, Bf, N, U + (long long)P0 * N2, N, np * N, N,
-                                                  (int)mN, 1.0, 1.0), 1)));
+        GF2_TRY((df_gemm<T, false, false, T>(c, mk(Pi, m, Bf, N2, U, N2, m, (int)N2, m, -2.0), 1)));
+        if (tensor) {
+            // Y[P][b][c] = B^P G, Z[Q][a][b] = B^Q Gb (rows (P, b) of B)
+            GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bf, N, G, N, Y, N, (int)mN, N, N), 1)));
+            GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bf, N, Gb, N, Z, N, (int)mN, N, N), 1)));
+            // V[(a,b)][(c,j)] = sum_Q Z[Q][(a,b)] B[Q][(c,j)]
+            GF2_TRY((df_gemm<T, true, false, T>(c, mk(Z, N2, Bf, N2, V, N2, (int)N2, (int)N2, m), 1)));
+            hipLaunchKernelGGL(k_df_permute<T>, dim3((unsigned)((N4 + 255) / 256)), dim3(256), 0,
+                               c->stream, N, (const T *)V, Vp);
+            GF2_HIP(hipGetLastError());
+            // U[P][(a,j)] += sum_{(b,c)} Y[P][(b,c)] Vp[(b,c)][(a,j)]
+            GF2_TRY((df_gemm<T, false, false, T>(c, mk(Y, N2, Vp, N2, U, N2, m, (int)N2, (int)N2, 1.0, 1.0),
+                                                  1)));
+        } else {
+            // Zt = Bt Gb; Tx^P = Zt Y^P, then U[P0 ..] += Tx B
+            GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bt, N, Gb, N, Zt, N, (int)mN, N, N), 1)));
+            for (int P0 = 0; P0 < m; P0 += pc) {
+                const int np = std::min(pc, m - P0);
+                DfGemm g = mk(Zt, N, Yt + (long long)P0 * N, mN, Tx, N, (int)mN, N, N);
+                g.sA = 0; g.sB = N; g.sC = mN2;
+                GF2_TRY((df_gemm<T, false, false, T>(c, g, np)));
+                GF2_TRY((df_gemm<T, false, false, T>(c, mk(Tx, mN, Bf, N, U + (long long)P0 * N2, N, np * N,
+                                                          N, (int)mN, 1.0, 1.0), 1)));
+            }
         }
         // Sigma(tau_k) = Yt U (K = (P, b))
         double *Sk = Sigma_tau + k * N2;
-        GF2_TRY((df_gemm<T, false, double>(c, mk(Yt, mN, U, N, Sk, N, N, N, (int)mN), 1)));
+        GF2_TRY((df_gemm<T, false, false, double>(c, mk(Yt, mN, U, N, Sk, N, N, N, (int)mN), 1)));
         hipLaunchKernelGGL(k_df_mirror, dim3((unsigned)((N2 + 255) / 256)), dim3(256), 0, c->stream, N, Sk);
         GF2_HIP(hipGetLastError());
         if (c->prof) prof_end(c, ph, flops);

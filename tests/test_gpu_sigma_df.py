@@ -94,20 +94,51 @@ def test_sigma_df_n100_sampled(torch, prec):
     g.close()
 
 
-def test_sigma_df_n160_chunked(torch):
-    """N=160 with 640 factors: the exchange products of one tau point exceed
-    the 1 GiB chunk, so P runs in chunks; one tau point against the dense
+@pytest.mark.parametrize("route", ["pair", "tensor"])
+def test_sigma_df_n160(torch, route):
+    """N=160 with 640 factors, both routes of the exchange term (pair route: the
+    products of one tau point exceed the 1 GiB chunk, so P runs in chunks;
+    tensor route: two 5.2 GB n^4 arrays); one tau point against the dense
     oracle contraction."""
+    import os
     n, ntau = 160, 4
-    print("sigma_df n=160 naux=640 fp64", flush=True)
+    print(f"sigma_df n=160 naux=640 fp64 {route}", flush=True)
     s = generic_system(n, 400, naux=640, half_band=16, diag=(-3.0, -0.3), beta=200.0, ntau=ntau)
     Gt = random_tau_stack(np.random.default_rng(9), ntau, n, scale=0.05)
     ref = O.sigma_tau(Gt, s.v, taus=[1])
     g = _gf2(s)
-    got = g.sigma_tau_df(_dev(torch, Gt), "fp64").cpu().numpy()[[1]]
+    os.environ["GF2_DF_ROUTE"] = route
+    try:
+        got = g.sigma_tau_df(_dev(torch, Gt), "fp64").cpu().numpy()[[1]]
+    finally:
+        os.environ.pop("GF2_DF_ROUTE", None)
     err = _relerr(got, ref)
     print(f"  rel err {err:.3e}", flush=True)
     assert err <= TOL["fp64"]
+    g.close()
+
+
+@pytest.mark.parametrize("n,naux", [(17, 40), (33, 7), (24, 72)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sigma_df_routes_agree(torch, n, naux, prec):
+    """The pair and the tensor route of the exchange term, each forced, against
+    the oracle's factored form (the automatic choice takes the tensor route
+    when naux > n)."""
+    import os
+    print(f"sigma_df routes n={n} naux={naux} {prec}", flush=True)
+    s = generic_system(n, 800 + n, naux=naux, beta=20.0, ntau=5)
+    Gt = random_tau_stack(np.random.default_rng(n), 5, n)
+    ref = O.sigma_tau_df(Gt, s.B)
+    g = _gf2(s)
+    try:
+        for route in ("pair", "tensor"):
+            os.environ["GF2_DF_ROUTE"] = route
+            got = g.sigma_tau_df(_dev(torch, Gt), prec).cpu().numpy()
+            err = _relerr(got, ref)
+            print(f"  {route}: rel err {err:.3e}", flush=True)
+            assert err <= TOL[prec]
+    finally:
+        os.environ.pop("GF2_DF_ROUTE", None)
     g.close()
 
 
