@@ -1951,11 +1951,21 @@ struct SigPlan {
     const void *V = nullptr, *W2 = nullptr;
 };
 
-static int sigma_bmax(int n, int mode) {
+// Largest tau batch.  T1 and X of b tau points take b (esz + t1sz) n^4 bytes;
+// the batch gets up to 48 GiB of them (at n = 100 in FP32, 64 tau points: then
+// b n = 6400 rows fill whole 128-row blocks of the first transform and the
+// final contraction), and at most half of the device memory that is free or
+// already held by these two buffers.  Every batch size gives bitwise the same
+// Sigma(tau), so the choice only moves time.
+static int sigma_bmax(const gf2_ctx *c, int mode) {
+    const size_t n = (size_t)c->n;
     const size_t esz = (mode == MODE_F64) ? 8 : 4;
     const size_t t1sz = split_planes(mode) ? 2 * (size_t)split_planes(mode) : esz;   // T1 element
-    const size_t N4 = (size_t)n * n * n * n;
-    const size_t budget = (size_t)16 << 30;   // T1 + X
+    const size_t N4 = n * n * n * n;
+    size_t budget = (size_t)48 << 30;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+        budget = std::min(budget, (fr + c->sig_T1.bytes + c->sig_X.bytes) / 2);
     return (int)std::min<size_t>(std::max<size_t>(1, budget / (N4 * (esz + t1sz))), 64);
 }
 
@@ -1991,7 +2001,7 @@ static int plan_init(gf2_ctx *c, int ntau, int prec, const double *G, double *Si
     p.s1_bk = (s1_mode(p.mode) == MODE_F32 && n % 16 != 0 && n % 20 == 0) ? 20 : 16;
     if (s1_mode(p.mode) == MODE_F32 && (sh.s1_bk == 16 || sh.s1_bk == 20)) p.s1_bk = sh.s1_bk;
     p.s1_nt = (sh.s1_nt >= 1 && sh.s1_nt <= 8) ? sh.s1_nt : 0;
-    const int bmax = sigma_bmax(n, p.mode);
+    const int bmax = sigma_bmax(c, p.mode);
     p.sh.b = std::max(1, std::min(sh.b > 0 ? sh.b : bmax, std::min(bmax, ntau)));
     const int wmax = (p.mode == MODE_F64) ? max_waves<MODE_F64>(p.KT)
                      : (p.mode == MODE_F32) ? max_waves<MODE_F32>(p.KT) : 8;
@@ -2254,7 +2264,7 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
     const char *env = std::getenv("GF2_SIGMA_TUNE");
     SigShape best{};
     if (!(env && env[0] == '0')) {
-        const int bmax = std::min(sigma_bmax(c->n, prec), ntau);
+        const int bmax = std::min(sigma_bmax(c, prec), ntau);
         std::vector<int> bs;
         for (int b : {bmax, (bmax + 1) / 2, (bmax + 3) / 4})
             if (b >= 1 && std::find(bs.begin(), bs.end(), b) == bs.end()) bs.push_back(b);
