@@ -2240,6 +2240,11 @@ struct TuneKey {
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, SigShape> g_tune;
+// Candidates are timed in order of preference (larger tau batches, fewer
+// waves, the rule's first-transform shape first); a later one replaces the
+// best so far only when it is faster by more than 2%, so shapes within the
+// timing noise of each other do not swap from one process to the next.
+constexpr double kTuneMargin = 0.98;
 
 static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *Sig, SigShape &out) {
     // GF2_SIGMA_SHAPE="b,waves[,s4cb[,s1_bk,s1_nt]]" forces a shape (read on every
@@ -2293,7 +2298,7 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
                 float ms = 0.0f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 const double per_tau = ms / nb;
-                if (per_tau < best_t) {
+                if (per_tau < best_t * kTuneMargin) {
                     best_t = per_tau;
                     best = SigShape{b, p.sh.waves, p.sh.s4cb};
                 }
@@ -2329,7 +2334,7 @@ static int tuned_shape(gf2_ctx *c, int ntau, int prec, const double *G, double *
                 if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(GF2_EHIP, "autotuner: event"); break; }
                 float ms = 0.0f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_s1) {
+                if (ms < best_s1 * kTuneMargin) {
                     best_s1 = ms;
                     best.s1_bk = bn.first;
                     best.s1_nt = bn.second;
