@@ -99,7 +99,9 @@ __device__ __forceinline__ void wave_sync() {
 
 // Rotate a value by k lanes within each row of 16 lanes (DPP row_ror:k).
 template <int K> __device__ __forceinline__ int ror16(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xF, 0xF, false);
+    // every lane reads a valid source lane, so no fallback value is needed
+    // (update_dpp with an explicit one costs a move per call)
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + K, 0xF, 0xF, false);
 }
 template <int K> __device__ __forceinline__ double ror16(double v) {
     const long long b = __double_as_longlong(v);
@@ -241,11 +243,13 @@ __device__ __forceinline__ void dyson_body(const DysonJob &a, const int lb, cons
                         for (int ia = 0; ia < RA; ++ia) {
                             const int i = tr + DY_TR * ia;
                             const double vr = mr[ia][jb], vi = mi[ia][jb];
-                            sh_f[buf][i] = i == rp ? make_double2(1.0 - ip.x, -ip.y)
-                                                   : make_double2(vr * ip.x - vi * ip.y, vr * ip.y + vi * ip.x);
+                            sh_f[buf][i] = make_double2(fma(vr, ip.x, -(vi * ip.y)), fma(vi, ip.x, vr * ip.y));
                             mr[ia][jb] = 0.0;
                             mi[ia][jb] = 0.0;
                         }
+                        // then the pivot row's owner lane overwrites its factor with
+                        // 1 - 1/p (one lane, so its two LDS writes stay in order)
+                        if (tr == (rp & (DY_TR - 1))) sh_f[buf][rp] = make_double2(1.0 - ip.x, -ip.y);
                         if (tr == 0) sh_r[buf] = rk;
                     }
                 }
@@ -472,18 +476,14 @@ __device__ __forceinline__ void dyson_wave(const DysonJob &a, const int lb, cons
                         for (int ia = 0; ia < RA; ++ia) {
                             const int i = tr + 16 * ia;
                             const double vx = mr[ia][jb], vy = mi[ia][jb];
-                            double fx = vx * ip.x - vy * ip.y;
-                            double fy = vx * ip.y + vy * ip.x;
-                            if (i == r) {
-                                fx = 1.0 - ip.x;
-                                fy = -ip.y;
-                            }
-                            fv[i] = make_double2(fx, fy);
+                            fv[i] = make_double2(fma(vx, ip.x, -(vy * ip.y)), fma(vx, ip.y, vy * ip.x));
                             mr[ia][jb] = 0.0;   // preset column k
                             mi[ia][jb] = 0.0;
                         }
                     }
                 }
+                // the pivot row's owner lane overwrites its factor with 1 - 1/p
+                if (r >= 0 && tr == (r & 15)) fv[r] = make_double2(1.0 - ip.x, -ip.y);
                 if (tr == 0) s_r[wv] = r;
             }
             wave_sync();
