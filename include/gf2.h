@@ -172,7 +172,13 @@ int gf2_set_system(gf2_ctx *ctx, int n, const double *S, const double *h, const 
  * entries j >= i are computed and (i, j), j < i, is a copy of (j, i).
  * prec: GF2_PREC_*.  dims->n must equal the n of gf2_set_system;
  * nelec, niw are ignored.  Returns GF2_ENONFINITE if the result holds a
- * NaN or Inf.
+ * NaN or Inf, GF2_ENOMEM if the workspace cannot be allocated.
+ * Workspace (owned by the context, kept between calls): the first and
+ * second transforms' intermediates of a batch of tau points, at most 64
+ * points, 48 GiB and half of the device memory free at the call (n = 100,
+ * FP32: 64 points, 51 GB).  The first call for an (n, ntau, prec) class in a
+ * process also times candidate batch and tile shapes on the input; every
+ * shape gives bitwise the same result.
  */
 int gf2_sigma_tau(gf2_ctx *ctx, const gf2_dims *dims, int prec,
                   const double *G_tau, double *Sigma_tau);
