@@ -61,6 +61,7 @@ struct DfGemm {
     int kz, split;
     double alpha, beta;
     double *part;
+    int ctrans;   // C(r, c) lives at C[c ldc + r] (through FP64 partials and k_df_reduce_t)
 };
 
 constexpr int DF_THREADS = 256;
@@ -216,6 +217,34 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
 }
 
 // C(r, c) = alpha sum_z part[z][r][c] + beta C(r, c), slices added in order.
+// The same with C(r, c) at C[c ldc + r]: 32 x 32 tiles through LDS, so that both
+// the partials and C are read and written along rows.  Block 32 x 8 threads.
+template <class OutT>
+__global__ void k_df_reduce_t(int M, int N, int nz, const double *__restrict__ part, OutT *C,
+                              long long ldc, double alpha, double beta) {
+    __shared__ double t[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const long long MN = (long long)M * N;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        double s = 0.0;
+        if (r < M && c < N)
+            for (int z = 0; z < nz; ++z) s += part[z * MN + (long long)r * N + c];
+        t[i][tx] = s;
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (r < M && c < N) {
+            OutT *cp = C + (long long)c * ldc + r;
+            double o = alpha * t[tx][i];
+            if (beta != 0.0) o += beta * (double)*cp;
+            *cp = (OutT)o;
+        }
+    }
+}
+
 template <class OutT>
 __global__ void k_df_reduce(int M, int N, int nz, const double *__restrict__ part, OutT *C,
                             long long ldc, double alpha, double beta) {
@@ -273,11 +302,20 @@ __global__ void k_df_permute(int n, const T *__restrict__ V, T *__restrict__ Vp)
     Vp[idx] = V[((a * n + b) * n + c) * n + j];
 }
 
-// Column tiles per block: ceil(N/16) tiles in the fewest blocks of <= 8.
+// Column tiles per block: ceil(N/16) tiles in the fewest blocks of <= 8, or, when
+// those would carry more than 5% idle tiles, in blocks of 4..8 tiles that divide
+// them exactly (N = 400: 5 blocks of 5 tiles instead of 4 of 7).
 void df_col_blocking(int N, int &nt, int &nblk) {
     const int tiles = (N + 15) / 16;
     nblk = (tiles + 7) / 8;
     nt = (tiles + nblk - 1) / nblk;
+    if ((nblk * nt - tiles) * 20 > nblk * nt)
+        for (int e = 8; e >= 4; --e)
+            if (tiles % e == 0) {
+                nt = e;
+                nblk = tiles / e;
+                break;
+            }
 }
 
 template <class T, bool AT, bool BT, class OutT>
@@ -307,11 +345,14 @@ int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
     int nz = batch;
     g.split = 0;
     g.kz = g.K;
-    if (batch == 1 && wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE) {
-        long long s = std::min<long long>((DF_TARGET_WG + wg - 1) / wg, g.K / DF_MIN_KSLICE);
+    if (g.ctrans && batch != 1) return fail(GF2_EINVAL, "gf2_sigma_tau_df: transposed batched GEMM");
+    if (batch == 1 && (g.ctrans || (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE))) {
+        long long s = 1;
+        if (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE)
+            s = std::min<long long>((DF_TARGET_WG + wg - 1) / wg, g.K / DF_MIN_KSLICE);
         const int kz = (int)(((g.K + s - 1) / s + DF_BK - 1) / DF_BK * DF_BK);
         s = (g.K + kz - 1) / kz;
-        if (s > 1) {
+        if (s > 1 || g.ctrans) {
             GF2_TRY(c->df_part.ensure((size_t)s * g.M * g.N * sizeof(double)));
             g.split = 1;
             g.kz = kz;
@@ -321,7 +362,12 @@ int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
     }
     df_launch<T, AT, BT, OutT>(nt, dim3((unsigned)rblk, (unsigned)nblk, (unsigned)nz), c->stream, g);
     GF2_HIP(hipGetLastError());
-    if (g.split) {
+    if (g.split && g.ctrans) {
+        hipLaunchKernelGGL(k_df_reduce_t<OutT>, dim3((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32)),
+                           dim3(32, 8), 0, c->stream, g.M, g.N, nz, (const double *)g.part,
+                           static_cast<OutT *>(g.C), g.ldc, g.alpha, g.beta);
+        GF2_HIP(hipGetLastError());
+    } else if (g.split) {
         const long long MN = (long long)g.M * g.N;
         hipLaunchKernelGGL(k_df_reduce<OutT>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, c->stream,
                            g.M, g.N, nz, (const double *)g.part, static_cast<OutT *>(g.C), g.ldc, g.alpha,
@@ -406,9 +452,13 @@ int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau
             hipLaunchKernelGGL(k_df_permute<T>, dim3((unsigned)((N4 + 255) / 256)), dim3(256), 0,
                                c->stream, N, (const T *)V, Vp);
             GF2_HIP(hipGetLastError());
-            // U[P][(a,j)] += sum_{(b,c)} Y[P][(b,c)] Vp[(b,c)][(a,j)]
-            GF2_TRY((df_gemm<T, false, false, T>(c, mk(Y, N2, Vp, N2, U, N2, m, (int)N2, (int)N2, 1.0, 1.0),
-                                                  1)));
+            // U[P][(a,j)] += sum_{(b,c)} Y[P][(b,c)] Vp[(b,c)][(a,j)], computed as its
+            // transpose (rows (a, j), columns P): the m columns then fill whole
+            // 16-wide tiles (the m rows of the direct form fill 128-row blocks only
+            // partly: 400 of 512), and the reduction adds it into U transposed back
+            DfGemm g = mk(Vp, N2, Y, N2, U, N2, (int)N2, m, (int)N2, 1.0, 1.0);
+            g.ctrans = 1;
+            GF2_TRY((df_gemm<T, true, true, T>(c, g, 1)));
         } else {
             // Zt = Bt Gb; Tx^P = Zt Y^P, then U[P0 ..] += Tx B
             GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bt, N, Gb, N, Zt, N, (int)mN, N, N), 1)));
