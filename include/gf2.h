@@ -205,7 +205,7 @@ int gf2_set_df_factors(gf2_ctx *ctx, int naux, const double *B);
  * flops per tau point; the exchange term is taken either as the products of
  * every factor pair (4 naux^2 n^3 flops) or through the n^4 tensor
  * sum_Q (B^Q Gb) (x) B^Q (4 naux n^4 flops), the latter when naux > n and
- * its two n^4 arrays fit in 16 GiB (GF2_DF_ROUTE=pair|tensor in the
+ * its n^4 array fits in 16 GiB (GF2_DF_ROUTE=pair|tensor in the
  * environment forces one).  Arguments and output as gf2_sigma_tau (G_tau and Sigma_tau
  * device [ntau][n][n] FP64, G symmetric, Sigma returned exactly symmetric);
  * prec: GF2_PREC_FP64 (FP64 MFMA) or GF2_PREC_FP32 (FP32 MFMA and FP32
@@ -213,7 +213,7 @@ int gf2_set_df_factors(gf2_ctx *ctx, int naux, const double *B);
  * Errors: GF2_ESTATE without factors; GF2_EINVAL for another prec, a
  * dims->n that differs from the system, ntau < 4, aliasing, NULL pointers;
  * GF2_ENOMEM if the workspace (5 naux n^2 + 2 n^2 + naux^2 elements, the
- * split-K partial sums, and 1 GiB of pair products or the two n^4 arrays)
+ * split-K partial sums, and 1 GiB of pair products or the n^4 array)
  * cannot be allocated;
  * GF2_ENONFINITE for a NaN or Inf in the result.
  */

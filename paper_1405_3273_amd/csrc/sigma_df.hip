@@ -62,6 +62,7 @@ struct DfGemm {
     double alpha, beta;
     double *part;
     int ctrans;   // C(r, c) lives at C[c ldc + r] (through FP64 partials and k_df_reduce_t)
+    int pn;       // > 0: C(a pn + b, c pn + j) lives at C[((b pn + c) pn + a) pn + j] (no split)
 };
 
 constexpr int DF_THREADS = 256;
@@ -208,7 +209,13 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
                 if (g.split) {
                     g.part[((long long)z * g.M + m) * g.N + n] = val;
                 } else {
-                    OutT *cp = static_cast<OutT *>(g.C) + (long long)z * g.sC + m * g.ldc + n;
+                    long long off = (long long)z * g.sC + m * g.ldc + n;
+                    if (g.pn > 0) {   // regrouped output (16 consecutive j per row of lanes)
+                        const int pn = g.pn, mi = (int)m;
+                        const int a = mi / pn, b = mi - a * pn, cq = n / pn, j = n - cq * pn;
+                        off = (((long long)b * pn + cq) * pn + a) * pn + j;
+                    }
+                    OutT *cp = static_cast<OutT *>(g.C) + off;
                     double o = g.alpha * val;
                     if (g.beta != 0.0) o += g.beta * (double)*cp;
                     *cp = (OutT)o;
@@ -291,16 +298,6 @@ __global__ void k_df_mirror(int n, double *S) {
     if (j < i) S[idx] = S[(long long)j * n + i];
 }
 
-// Vp[b][c][a][j] = V[a][b][c][j] (the exchange tensor regrouped so that the
-// last product contracts (b, c) as one row index)
-template <class T>
-__global__ void k_df_permute(int n, const T *__restrict__ V, T *__restrict__ Vp) {
-    const long long n2 = (long long)n * n;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n2 * n2) return;
-    const long long j = idx % n, t1 = idx / n, a = t1 % n, t2 = t1 / n, c = t2 % n, b = t2 / n;
-    Vp[idx] = V[((a * n + b) * n + c) * n + j];
-}
 
 // Column tiles per block: ceil(N/16) tiles in the fewest blocks of <= 8, or, when
 // those would carry more than 5% idle tiles, in blocks of 4..8 tiles that divide
@@ -346,7 +343,8 @@ int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
     g.split = 0;
     g.kz = g.K;
     if (g.ctrans && batch != 1) return fail(GF2_EINVAL, "gf2_sigma_tau_df: transposed batched GEMM");
-    if (batch == 1 && (g.ctrans || (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE))) {
+    if (g.ctrans && g.pn > 0) return fail(GF2_EINVAL, "gf2_sigma_tau_df: transposed regrouped GEMM");
+    if (batch == 1 && g.pn == 0 && (g.ctrans || (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE))) {
         long long s = 1;
         if (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE)
             s = std::min<long long>((DF_TARGET_WG + wg - 1) / wg, g.K / DF_MIN_KSLICE);
@@ -390,7 +388,7 @@ DfGemm mk(const void *A, long long lda, const void *B, long long ldb, void *C, l
 
 // Exchange products held at once: at most this many bytes (whole P slabs).
 constexpr size_t DF_T_BYTES = size_t(1) << 30;
-// The tensor route's two N^4 arrays may take at most this many bytes.
+// The tensor route's N^4 array may take at most this many bytes.
 constexpr size_t DF_V_BYTES = size_t(16) << 30;
 
 // Two evaluations of the exchange term, equal up to rounding:
@@ -398,7 +396,8 @@ constexpr size_t DF_V_BYTES = size_t(16) << 30;
 //                 chunks of P: 4 m^2 N^3 flops, O(m N^2) memory besides a 1 GiB chunk;
 //   tensor route: V[(a,b)][(c,j)] = sum_Q Z^Q_ab B^Q_cj once (one GEMM over Q), then
 //                 U^P_aj += sum_{b,c} Y^P_bc V[(a,b)][(c,j)] for all P (one GEMM over
-//                 (b, c)): 4 m N^4 flops and two N^4 arrays.
+//                 (b, c)): 4 m N^4 flops and one N^4 array (the first GEMM writes V
+//                 regrouped as Vp[(b,c)][(a,j)]).
 // The tensor route needs fewer flops when m > N (every configuration here), the pair
 // route less memory; the tensor route is taken when m > N and its arrays fit in
 // DF_V_BYTES.  GF2_DF_ROUTE=pair|tensor in the environment forces one (tests).
@@ -406,7 +405,7 @@ template <class T>
 int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau) {
     const int N = c->n, m = c->df_m, ntau = d->ntau;
     const long long N2 = (long long)N * N, N4 = N2 * N2, mN = (long long)m * N, mN2 = mN * N;
-    bool tensor = m > N && (size_t)(2 * N4) * sizeof(T) <= DF_V_BYTES;
+    bool tensor = m > N && (size_t)N4 * sizeof(T) <= DF_V_BYTES;
     if (const char *e = std::getenv("GF2_DF_ROUTE")) {
         if (e[0] == 'p') tensor = false;
         if (e[0] == 't') tensor = true;
@@ -415,11 +414,11 @@ int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau
     const int pc = (int)std::max<size_t>(1, std::min<size_t>(m, DF_T_BYTES / slab));
     const size_t ws = (size_t)(2 * N2 + 5 * mN2 + (long long)m * m) * sizeof(T);
     GF2_TRY(c->df_ws.ensure(ws));
-    GF2_TRY(c->df_T.ensure(tensor ? (size_t)(2 * N4) * sizeof(T) : (size_t)pc * slab));
+    GF2_TRY(c->df_T.ensure(tensor ? (size_t)N4 * sizeof(T) : (size_t)pc * slab));
     T *G = c->df_ws.as<T>(), *Gb = G + N2, *Yt = Gb + N2, *Zt = Yt + mN2, *W = Zt + mN2,
       *U = W + mN2, *Y = U + mN2, *Pi = Y + mN2;
     T *Tx = c->df_T.as<T>();
-    T *V = Tx, *Vp = Tx + N4;                        // tensor route
+    T *Vp = Tx;                                      // tensor route
     T *Z = Zt;                                       // tensor route: Z[Q][a][b] in Zt's space
     const T *Bf = sizeof(T) == 8 ? (const T *)c->df_B64.ptr : (const T *)c->df_B32.ptr;
     const T *Bt = sizeof(T) == 8 ? (const T *)c->df_Bt64.ptr : (const T *)c->df_Bt32.ptr;
@@ -447,11 +446,13 @@ int df_run(gf2_ctx *c, const gf2_dims *d, const double *G_tau, double *Sigma_tau
             // Y[P][b][c] = B^P G, Z[Q][a][b] = B^Q Gb (rows (P, b) of B)
             GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bf, N, G, N, Y, N, (int)mN, N, N), 1)));
             GF2_TRY((df_gemm<T, false, false, T>(c, mk(Bf, N, Gb, N, Z, N, (int)mN, N, N), 1)));
-            // V[(a,b)][(c,j)] = sum_Q Z[Q][(a,b)] B[Q][(c,j)]
-            GF2_TRY((df_gemm<T, true, false, T>(c, mk(Z, N2, Bf, N2, V, N2, (int)N2, (int)N2, m), 1)));
-            hipLaunchKernelGGL(k_df_permute<T>, dim3((unsigned)((N4 + 255) / 256)), dim3(256), 0,
-                               c->stream, N, (const T *)V, Vp);
-            GF2_HIP(hipGetLastError());
+            // V[(a,b)][(c,j)] = sum_Q Z[Q][(a,b)] B[Q][(c,j)], written regrouped as
+            // Vp[(b,c)][(a,j)] by the GEMM's epilogue
+            {
+                DfGemm g = mk(Z, N2, Bf, N2, Vp, N2, (int)N2, (int)N2, m);
+                g.pn = N;
+                GF2_TRY((df_gemm<T, true, false, T>(c, g, 1)));
+            }
             // U[P][(a,j)] += sum_{(b,c)} Y[P][(b,c)] Vp[(b,c)][(a,j)], computed as its
             // transpose (rows (a, j), columns P): the m columns then fill whole
             // 16-wide tiles (the m rows of the direct form fill 128-row blocks only

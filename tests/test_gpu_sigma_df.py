@@ -98,7 +98,7 @@ def test_sigma_df_n100_sampled(torch, prec):
 def test_sigma_df_n160(torch, route):
     """N=160 with 640 factors, both routes of the exchange term (pair route: the
     products of one tau point exceed the 1 GiB chunk, so P runs in chunks;
-    tensor route: two 5.2 GB n^4 arrays); one tau point against the dense
+    tensor route: one 5.2 GB n^4 array); one tau point against the dense
     oracle contraction."""
     import os
     n, ntau = 160, 4
