@@ -85,7 +85,7 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
     constexpr int BN = 16 * NT;
     constexpr int SA = DF_BM + 16;                    // padded row strides
     constexpr int SB = BN + ((16 - BN % 32) + 32) % 32;
-    __shared__ T As[DF_BK][SA];
+    __shared__ __attribute__((aligned(16))) T As[DF_BK][SA];
     __shared__ T Bs[DF_BK][SB];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -118,14 +118,40 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
 
     constexpr int A_PER = DF_BK * DF_BM / DF_THREADS;
     constexpr int B_PER = (DF_BK * BN + DF_THREADS - 1) / DF_THREADS;
+    // FP32, transposed A with aligned rows: thread t takes A_PER consecutive rows of
+    // chunk row t / 16 as 16-byte loads (one LDS row segment), else one element per
+    // step (FP64 keeps the element steps: its 16-byte form measured slower).
+    constexpr int VEC = 16 / (int)sizeof(T);
+    static_assert(DF_BM / A_PER * DF_BK == DF_THREADS && A_PER % VEC == 0, "A chunk layout");
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    const bool avec = AT && !F64 && g.lda % VEC == 0 && g.sA % VEC == 0 && (uintptr_t)A % 16 == 0;
+    const int ak = tid / (DF_BM / A_PER), am = (tid % (DF_BM / A_PER)) * A_PER;
     T ra[A_PER], rb[B_PER];
     auto load = [&](int kb) {
+        if (avec) {
+            const long long gr = r0 + am;
+            const int gk = kb + ak;
+            const T *src = A + (long long)gk * g.lda + gr;
+            if (gk < K && gr + A_PER <= g.M) {
 #pragma unroll
-        for (int e = 0; e < A_PER; ++e) {
-            const int idx = tid + e * DF_THREADS;
-            const long long gr = r0 + (AT ? idx % DF_BM : idx / DF_BK);
-            const int gk = kb + (AT ? idx / DF_BM : idx % DF_BK);
-            ra[e] = (gr < g.M && gk < K) ? (AT ? A[(long long)gk * g.lda + gr] : A[gr * g.lda + gk]) : T(0);
+                for (int v = 0; v < A_PER / VEC; ++v) {
+                    const vec_t t = *reinterpret_cast<const vec_t *>(src + VEC * v);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ra[VEC * v + e] = t[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < A_PER; ++e) ra[e] = (gk < K && gr + e < g.M) ? src[e] : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < A_PER; ++e) {
+                const int idx = tid + e * DF_THREADS;
+                const long long gr = r0 + (AT ? idx % DF_BM : idx / DF_BK);
+                const int gk = kb + (AT ? idx / DF_BM : idx % DF_BK);
+                ra[e] = (gr < g.M && gk < K) ? (AT ? A[(long long)gk * g.lda + gr] : A[gr * g.lda + gk])
+                                             : T(0);
+            }
         }
 #pragma unroll
         for (int e = 0; e < B_PER; ++e) {
@@ -138,11 +164,21 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
         }
     };
     auto store = [&]() {
+        if (avec) {
 #pragma unroll
-        for (int e = 0; e < A_PER; ++e) {
-            const int idx = tid + e * DF_THREADS;
-            if constexpr (AT) As[idx / DF_BM][idx % DF_BM] = ra[e];
-            else As[idx % DF_BK][idx / DF_BK] = ra[e];
+            for (int v = 0; v < A_PER / VEC; ++v) {
+                vec_t t;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) t[e] = ra[VEC * v + e];
+                *reinterpret_cast<vec_t *>(&As[ak][am + VEC * v]) = t;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < A_PER; ++e) {
+                const int idx = tid + e * DF_THREADS;
+                if constexpr (AT) As[idx / DF_BM][idx % DF_BM] = ra[e];
+                else As[idx % DF_BK][idx / DF_BK] = ra[e];
+            }
         }
 #pragma unroll
         for (int e = 0; e < B_PER; ++e) {
