@@ -382,8 +382,21 @@ int df_gemm(gf2_ctx *c, DfGemm g, int batch) {
     if (g.ctrans && g.pn > 0) return fail(GF2_EINVAL, "gf2_sigma_tau_df: transposed regrouped GEMM");
     if (batch == 1 && g.pn == 0 && (g.ctrans || (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE))) {
         long long s = 1;
-        if (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE)
+        if (wg < DF_TARGET_WG && g.K >= 2 * DF_MIN_KSLICE) {
             s = std::min<long long>((DF_TARGET_WG + wg - 1) / wg, g.K / DF_MIN_KSLICE);
+            // up to twice as many slices when that fills the last round of resident
+            // workgroups better (two per CU, one for the widest FP32 tile)
+            int cus = 256;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+            const double slots = (double)cus * ((sizeof(T) == 8 || nt <= 7) ? 2 : 1);
+            auto fill = [&](long long q) {
+                const double rounds = (double)(wg * q) / slots;
+                return rounds / std::ceil(rounds);
+            };
+            const long long s0 = s, smax = std::min<long long>(2 * s0, g.K / DF_MIN_KSLICE);
+            for (long long q = s0 + 1; q <= smax; ++q)
+                if (fill(q) > fill(s) + 0.01) s = q;
+        }
         const int kz = (int)(((g.K + s - 1) / s + DF_BK - 1) / DF_BK * DF_BK);
         s = (g.K + kz - 1) / kz;
         if (s > 1 || g.ctrans) {

@@ -39,9 +39,10 @@ def _relerr(got, ref):
 
 
 # n, naux, ntau: one and several 16-wide tiles, ragged tails, one factor,
-# naux below and above n, naux giving a 400-column Pi (split-K over N^2)
-CASES = [(1, 1, 4), (2, 3, 5), (5, 15, 6), (16, 16, 4), (17, 40, 5), (33, 7, 4), (40, 120, 4),
-         (20, 400, 4)]
+# naux below and above n, naux above n^2 (the tensor route's transposed exchange
+# GEMM with more columns than rows), naux giving a 400-column Pi (split-K over N^2)
+CASES = [(1, 1, 4), (2, 3, 5), (2, 5, 4), (3, 11, 4), (5, 15, 6), (16, 16, 4), (17, 40, 5),
+         (33, 7, 4), (40, 120, 4), (20, 400, 4)]
 
 
 @pytest.mark.parametrize("n,naux,ntau", CASES)
