@@ -73,13 +73,15 @@ constexpr int DF_FLUSH = 512 / DF_BK;     // FP32 form: chunks between FP64 flus
 
 // Two workgroups per CU (two waves per SIMD: one loads and stores its next
 // chunk while the other runs MFMAs), except for the widest FP32 tile, whose
-// FP64 flush registers would then spill.
-template <class T, int NT> struct DfWaves {
-    static constexpr int value = (sizeof(T) == 8 || NT <= 7) ? 2 : 1;
+// FP64 flush registers would then spill.  ONE: the launch's K is at most one
+// flush interval, so the FP32 accumulators are converted once at the end and
+// need no FP64 copy (the same sums; the widest tile then keeps two per CU).
+template <class T, int NT, bool ONE> struct DfWaves {
+    static constexpr int value = (sizeof(T) == 8 || NT <= 7 || ONE) ? 2 : 1;
 };
 
-template <class T, bool AT, bool BT, int NT, class OutT>
-__global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm(DfGemm g) {
+template <class T, bool AT, bool BT, int NT, class OutT, bool ONE>
+__global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT, ONE>::value)) void k_df_gemm(DfGemm g) {
     using acc_t = typename DfAcc<T>::type;
     constexpr bool F64 = sizeof(T) == 8;
     constexpr int BN = 16 * NT;
@@ -106,14 +108,17 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
     }
 
     acc_t acc[DF_RT][NT];
-    double accd[DF_RT][NT][4];
+    constexpr bool FLUSH = !F64 && !ONE;
+    double accd[FLUSH ? DF_RT : 1][FLUSH ? NT : 1][4];
 #pragma unroll
     for (int r = 0; r < DF_RT; ++r)
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             acc[r][c] = acc_t{0, 0, 0, 0};
+            if constexpr (FLUSH) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) accd[r][c][e] = 0.0;
+                for (int e = 0; e < 4; ++e) accd[r][c][e] = 0.0;
+            }
         }
 
     constexpr int A_PER = DF_BK * DF_BM / DF_THREADS;
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
                         acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf[c], acc[r][c], 0, 0, 0);
                 }
         }
-        if constexpr (!F64) {
+        if constexpr (FLUSH) {
             if ((ch + 1) % DF_FLUSH == 0 || ch + 1 == nch) {
 #pragma unroll
                 for (int r = 0; r < DF_RT; ++r)
@@ -241,7 +246,9 @@ __global__ __launch_bounds__(DF_THREADS, (DfWaves<T, NT>::value)) void k_df_gemm
                 const long long m = r0 + wave * (16 * DF_RT) + 16 * r + row;
                 const int n = c0 + 16 * c + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
-                const double val = F64 ? (double)acc[r][c][e] : accd[r][c][e];
+                double val;
+                if constexpr (FLUSH) val = accd[r][c][e];
+                else val = (double)acc[r][c][e];
                 if (g.split) {
                     g.part[((long long)z * g.M + m) * g.N + n] = val;
                 } else {
@@ -353,9 +360,16 @@ void df_col_blocking(int N, int &nt, int &nblk) {
 
 template <class T, bool AT, bool BT, class OutT>
 void df_launch(int nt, dim3 grid, hipStream_t s, const DfGemm &g) {
+    // FP32, widest tile, K of the launch within one flush interval: no FP64 copy
+    if constexpr (sizeof(T) == 4) {
+        if (nt == 8 && (g.split ? g.kz : g.K) <= DF_FLUSH * DF_BK) {
+            hipLaunchKernelGGL((k_df_gemm<T, AT, BT, 8, OutT, true>), grid, dim3(DF_THREADS), 0, s, g);
+            return;
+        }
+    }
     switch (nt) {
 #define GF2_DF_CASE(N_) \
-    case N_: hipLaunchKernelGGL((k_df_gemm<T, AT, BT, N_, OutT>), grid, dim3(DF_THREADS), 0, s, g); break;
+    case N_: hipLaunchKernelGGL((k_df_gemm<T, AT, BT, N_, OutT, false>), grid, dim3(DF_THREADS), 0, s, g); break;
         GF2_DF_CASE(1) GF2_DF_CASE(2) GF2_DF_CASE(3) GF2_DF_CASE(4)
         GF2_DF_CASE(5) GF2_DF_CASE(6) GF2_DF_CASE(7) GF2_DF_CASE(8)
 #undef GF2_DF_CASE
